@@ -1,0 +1,234 @@
+"""Benchmark: source points linearized per second (e, H, b), batched vs plain.
+
+Default workload: the global submap batch -- 500 synthetic submaps of
+50k-300k points (log-uniform), 0.5 m voxels, 5,000 submap-to-submap factors
+(submap i against i +- 3..7) -- linearized in FP32 with compensated
+accumulation, one captured hipGraph per step (upload poses, tile kernel,
+factor reduction, download results).  A step is one full linearization of the
+whole batch; inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+B_POINT = 36               # mu (12) + C (24), FP32, per (factor, source point)
+B_KEY = 8                  # one hash slot per (point, level)
+B_HIT = 36                 # voxel mean (12) + covariance (24) per hit
+B_FACTOR = 48 + 344        # pose in + e/H/b/inliers out per factor
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name, n_submaps):
+    import synth
+    t = time.time()
+    if name == "global":
+        cfg = synth.config3(n_submaps=n_submaps)
+        desc = {"workload": "global submap batch", "submaps": n_submaps, "factors": len(cfg["factors"]),
+                "points_per_submap": "50k-300k log-uniform", "voxel_m": 0.5, "levels": 1}
+    elif name == "odometry":
+        cfg = synth.config2()
+        desc = {"workload": "odometry batch", "factors": 20, "points_per_frame": cfg["sources"][0].n,
+                "voxel_m": [0.25, 0.5, 1.0, 2.0], "levels": 4}
+    elif name == "single":
+        cfg = synth.config1()
+        desc = {"workload": "single factor", "factors": 1, "source_points": 5000, "target_points": 20000,
+                "voxel_m": 0.5, "levels": 1}
+    else:
+        raise SystemExit("unknown workload " + name)
+    log("generated %s in %.1f s" % (name, time.time() - t))
+    return cfg, desc
+
+
+def algorithmic_bytes(cfg, inliers):
+    pts = sum(cfg["sources"][s].n for (s, _) in cfg["factors"])
+    L = inliers.shape[1]
+    hits = int(inliers.sum())
+    return pts * B_POINT + pts * L * B_KEY + hits * B_HIT + len(cfg["factors"]) * B_FACTOR, pts, hits
+
+
+def cpu_baseline(cfg, batch_out, budget_s=12.0):
+    """FP64 oracle on a bounded sample of the factors, on the host's cores."""
+    import oracle
+    oracle.build()
+    fac = cfg["factors"]
+    res = cfg["resolutions"]
+    cores = len(os.sched_getaffinity(0))
+    rng = np.random.default_rng(0)
+    order = rng.permutation(len(fac))
+    maps = {}
+
+    def get_factor(f):
+        s, t = fac[f]
+        if t not in maps:
+            tg = cfg["targets"][t]
+            maps[t] = oracle.VoxelMap(tg.xyz64(), tg.cov64(), res)
+        src = cfg["sources"][s]
+        return oracle.Factor(src.xyz64(), src.cov64(), maps[t], viewpoint=cfg["target_viewpoints"][f])
+
+    # calibrate with one factor, then size the sample for the budget
+    f0 = int(order[0])
+    of = get_factor(f0)
+    t = time.perf_counter()
+    of.linearize(cfg["poses"][f0])
+    one = time.perf_counter() - t
+    n_pts0 = cfg["sources"][fac[f0][0]].n
+    rate1 = n_pts0 / max(one, 1e-9)
+    want_pts = rate1 * cores * budget_s
+    sample, acc = [], 0
+    for f in order:
+        if acc >= want_pts and len(sample) >= cores:
+            break
+        sample.append(int(f))
+        acc += cfg["sources"][fac[int(f)][0]].n
+    factors = {f: get_factor(f) for f in sample}     # map builds outside the timed region
+
+    def run(f):
+        return f, factors[f].linearize(cfg["poses"][f])
+
+    t = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        results = dict(ex.map(run, sample))
+    dt = time.perf_counter() - t
+    pts = sum(cfg["sources"][fac[f][0]].n for f in sample)
+    # parity of the device results on the same sample (relative errors, C15 definitions)
+    worst = {"e": 0.0, "H": 0.0, "b": 0.0}
+    if batch_out is not None:
+        e, H, b = batch_out
+        for f, r in results.items():
+            for k, dev, ref in (("e", e[f], r["e"]), ("H", H[f], r["H"]), ("b", b[f], r["b"])):
+                nr = np.linalg.norm(ref)
+                err = 0.0 if nr == 0 and np.linalg.norm(dev) == 0 else float(np.linalg.norm(dev - ref) / max(nr, 1e-300))
+                worst[k] = max(worst[k], err)
+    return {"value": pts / dt, "unit": "source points/s", "cores": cores, "kind": "oracle",
+            "sample": "%d of %d factors (%d source points), FP64 C oracle, one factor per thread" % (
+                len(sample), len(fac), pts),
+            "seconds": dt}, worst
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="global", choices=["global", "odometry", "single"])
+    ap.add_argument("--submaps", type=int, default=500)
+    ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp64"])
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="only run this many batched steps (for profilers), print nothing else")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2407_10344_amd import vgicp
+
+    cfg, desc = make_workload(args.workload, args.submaps)
+    ctx = vgicp.Context(0)
+    t = time.time()
+    maps, srcs, batch = vgicp.build_workload(ctx, cfg, precision=args.precision, use_graph=True)
+    torch.cuda.synchronize()
+    log("device maps/sources/batch built in %.1f s" % (time.time() - t))
+    poses = vgicp.poses12(np.array(cfg["poses"]))
+    info = batch.info()
+    if not args.no_tune and args.profile_steps == 0:
+        t = time.time()
+        chosen = batch.tune(poses, reps=2)
+        info = batch.info()
+        log("autotuned %s in %.1f s" % (chosen, time.time() - t))
+
+    if args.profile_steps:
+        for _ in range(args.profile_steps):
+            batch.linearize(poses)
+        torch.cuda.synchronize()
+        log("profile run done")
+        return
+
+    for _ in range(args.warmup):
+        e, H, b, inl = batch.linearize(poses)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e, H, b, inl = batch.linearize(poses)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    B_alg, pts, hits = algorithmic_bytes(cfg, inl)
+    value = pts / dt
+
+    # dominant kernel time, HIP events on the library's stream
+    tk = batch.time_kernels(poses, reps=max(3, min(args.steps, 20)))
+    achieved = B_alg / (tk["tile_kernel_ms"] * 1e-3)
+
+    # plain per-factor path (one upload, launch, download and sync per factor)
+    plain_rate = None
+    if args.plain_steps > 0:
+        _, _, plain = vgicp.build_workload(ctx, cfg, precision=args.precision, use_graph=False, plain=True,
+                                           block=info["block_threads"], tile=info["tile_points"])
+        plain.linearize(poses)
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            ep, Hp, bp, _ = plain.linearize(poses)
+        plain_dt = (time.perf_counter() - t0) / args.plain_steps
+        plain_rate = pts / plain_dt
+        same = bool(np.array_equal(ep, e) and np.array_equal(Hp, H) and np.array_equal(bp, b))
+        plain.close()
+        log("plain per-factor: %.1f ms/step, identical results: %s" % (plain_dt * 1e3, same))
+
+    cpu, parity = (None, None)
+    if not args.no_cpu:
+        cpu, parity = cpu_baseline(cfg, (e, H, b))
+        log("cpu baseline", cpu, "parity on sample", parity)
+
+    dtype = {"fp32c": "f32", "fp32": "f32", "fp64": "f64"}[args.precision]
+    out = {
+        "metric": "source points linearized/sec (e,H,b), batched vs plain, at rel. err <=1e-5",
+        "value": value,
+        "unit": "source points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": dict(desc, precision=args.precision, total_source_points=pts, inlier_pairs=hits,
+                       hit_rate=hits / max(pts, 1), launch=info),
+        "plain": None if plain_rate is None else {"value": plain_rate, "unit": "source points/s",
+                                                  "batched_speedup": value / plain_rate},
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK, "traffic": None,
+                     "kernel": "k_tiles<lin,%s>" % args.precision, "kernel_ms": tk["tile_kernel_ms"],
+                     "reduce_ms": tk["reduce_ms"], "algorithmic_bytes": B_alg},
+        "cpu_baseline": cpu,
+        "parity_sample": parity,
+    }
+    print(json.dumps(out), flush=True)
+    batch.close()
+
+
+if __name__ == "__main__":
+    main()

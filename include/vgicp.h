@@ -1,0 +1,225 @@
+/*
+ * vgicp.h -- C ABI of the MI355X (gfx950) VGICP factor-linearization library.
+ *
+ * What it computes (GLIM, Koide et al. 2024, Sec. III-C "Matching Cost Factor"):
+ * a factor matches a source Gaussian point cloud {(mu_k, C_k)} into the
+ * multi-resolution Gaussian voxel map of a target cloud {(mu~, C~) per voxel,
+ * levels r_l = r_0 2^(l-1)}.  At a relative pose T = (R, t) that maps source
+ * points into the target frame, every source point is transformed
+ * (y = R mu + t), its voxel q = floor(y / r_l) is looked up at every level
+ * (Sec. III-C "Correspondence search"), and each hit contributes
+ *     d = mu~ - y,  W = (C~ + R C R^T)^-1,  e += d^T W d      (Eq. (em), Eq. (d2d))
+ *     J = [R (mu)x, -R],  H += J^T W J,  b += J^T W d         (Sec. III-C "Linearization")
+ * with W frozen at the linearization point.  All factors of a batch are
+ * linearized with one upload of the poses and one download of the results
+ * (Sec. III-C "Implementation").
+ *
+ * Conventions shared by every entry point:
+ *   - A pose is 12 doubles, row-major R (9) then t (3); it maps source-frame
+ *     points into the target frame.
+ *   - H (6x6, row-major) and b (6) are derivatives w.r.t. a right perturbation
+ *     T Exp(xi), xi = [omega; v] (rotation first).  e has no factor 1/2, so
+ *     e(T Exp(xi)) ~ e + 2 b^T xi + xi^T H xi and the Gauss-Newton step is
+ *     -H^-1 b.
+ *   - Covariances are 6 doubles per point: xx, xy, xz, yy, yz, zz.
+ *   - Resolutions are ascending and each is the previous one times a power of
+ *     two, and every resolution is itself a power of two (so y / r is exact).
+ *   - Voxel keys are limited to |q - q_origin| < 8192 per axis around the map
+ *     origin (the first point snapped to the coarsest voxel), and a level holds
+ *     fewer than 4,194,303 voxels.
+ *
+ * Error behaviour: every call returns a vg_status (0 = VG_OK).  No exception
+ * crosses the ABI.  On failure vg_last_error() returns a message that stays
+ * valid until the next call on the same thread.  Arguments are validated on
+ * the host before any device work is queued; a failed call leaves its outputs
+ * unspecified and its handles usable.
+ *
+ * Ownership: input arrays are read during the call and never retained;
+ * handles are owned by the caller and released with the matching *_destroy.
+ * A batch keeps references to its sources and voxel maps: destroying one of
+ * them while a batch uses it fails with VG_ERR_STATE.  Device pointers passed
+ * to *_async calls stay owned by the caller and must remain valid until the
+ * queued work completes on the context stream.
+ *
+ * Threading: a context and everything created from it must be used by one
+ * thread at a time.  Calls that share a context are ordered on its stream.
+ */
+#ifndef VGICP_H
+#define VGICP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VG_OK = 0,
+    VG_ERR_INVALID_ARG = -1, /* a pointer, size, pose or option is invalid */
+    VG_ERR_HIP = -2,         /* a HIP runtime call failed (message has the HIP string) */
+    VG_ERR_OOM = -3,         /* device or pinned host allocation failed */
+    VG_ERR_KEY_RANGE = -4,   /* a target voxel key lies outside the packable range */
+    VG_ERR_CAPACITY = -5,    /* too many voxels in one level */
+    VG_ERR_NOT_SPD = -6,     /* an input covariance is not symmetric positive definite */
+    VG_ERR_STATE = -7        /* handle in use, destroyed, or from another context */
+} vg_status;
+
+typedef enum {
+    VG_FP32_COMPENSATED = 0, /* FP32 per point in re-centred coordinates, Kahan per lane,
+                                FP64 across waves, tiles and factors (the default) */
+    VG_FP32 = 1,             /* absolute FP32 coordinates, FP32 accumulation end to end */
+    VG_FP64 = 2              /* FP64 data and arithmetic throughout */
+} vg_precision;
+
+typedef struct vg_context vg_context;
+typedef struct vg_voxelmap vg_voxelmap;
+typedef struct vg_source vg_source;
+typedef struct vg_batch vg_batch;
+
+/* Options of a factor batch.  Zero-initialize, then set what you need; a zero
+ * tuning field means "use the default, or the tuned value if tune_cache is set". */
+typedef struct {
+    int32_t precision;          /* a vg_precision value */
+    int32_t surface_validation; /* 1: discard a point when (mu - T^-1 c) . n > 0 (Sec. III-C,
+                                   Correspondence search); sources need normals, c is the
+                                   target viewpoint of the factor */
+    int32_t use_graph;          /* 1: replay a captured hipGraph [H2D, kernels, D2H] */
+    int32_t plain_per_factor;   /* 1: one launch, one upload, one download and one host
+                                   synchronization per factor (the per-factor loop the
+                                   batched mechanism replaces) */
+    int32_t block_threads;      /* 64, 128, 256 or 512 threads per workgroup; 0 = default */
+    int32_t tile_points;        /* source points per work tile, a multiple of 64; 0 = default */
+    int32_t blocks_per_cu;      /* persistent workgroups per compute unit; 0 = default */
+    const char* tune_cache;     /* NULL: no autotuning.  Otherwise a file path: tuned shapes
+                                   are read from it, or measured and appended to it */
+} vg_batch_options;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t that
+ * all work is queued on (borrowed, not destroyed); NULL creates a private one. */
+vg_status vg_context_create(int32_t device, void* hip_stream, vg_context** out);
+vg_status vg_context_destroy(vg_context* ctx);
+/* Thread-local message of the last failed call ("" if none). */
+const char* vg_last_error(void);
+/* Library version: major * 10000 + minor * 100 + patch. */
+int32_t vg_version(void);
+
+/* ---- voxel maps (Sec. III-C, Preprocessing) ------------------------------ */
+
+/* Build the Gaussian voxel map of a target cloud: for every level l, each point
+ * x falls in voxel floor(x / r_l); a voxel stores the average of its points'
+ * means and the average of their covariances (summed in FP64 in ascending point
+ * order).  xyz: n x 3, cov: n x 6 (host, FP64).  n may be 0 (empty map).
+ * Errors: VG_ERR_INVALID_ARG (non-finite input, bad resolutions, L outside
+ * 1..4), VG_ERR_KEY_RANGE, VG_ERR_CAPACITY, VG_ERR_OOM, VG_ERR_HIP. */
+vg_status vg_build_voxelmap(vg_context* ctx, const double* xyz, const double* cov, int64_t n,
+                            const double* resolutions, int32_t L, vg_voxelmap** out);
+/* Number of voxels of a level and the hash-table capacity (slots). */
+vg_status vg_voxelmap_info(const vg_voxelmap* map, int32_t level, int64_t* n_voxels,
+                           int64_t* capacity);
+/* Copy a level to the host in canonical order (ascending lexicographic key).
+ * Any output may be NULL.  keys: V x 3 absolute voxel coordinates; means: V x 3
+ * and covs: V x 6 in FP64; counts: V.  `n_voxels` is in/out: capacity of the
+ * outputs on entry, voxel count on return (VG_ERR_INVALID_ARG if too small). */
+vg_status vg_voxelmap_export(const vg_voxelmap* map, int32_t level, int64_t* n_voxels, int64_t* keys,
+                             double* means, double* covs, int64_t* counts);
+vg_status vg_voxelmap_destroy(vg_voxelmap* map);
+
+/* ---- source clouds ---------------------------------------------------- */
+
+/* Upload a source Gaussian cloud (host FP64: xyz n x 3, cov n x 6, normals n x 3
+ * or NULL).  The library reorders points internally along a Morton curve and
+ * stores them relative to per-64-point anchors; every per-point output of the
+ * library is reported in the caller's order.  Covariances must be SPD
+ * (VG_ERR_NOT_SPD otherwise). */
+vg_status vg_create_source(vg_context* ctx, const double* xyz, const double* cov, const double* normals,
+                           int64_t n, vg_source** out);
+/* Replace the source positions from a device buffer in caller order (n x 3,
+ * dtype 0 = float32, 1 = float64), stream-ordered; covariances and normals are
+ * kept.  Used to differentiate with respect to the points. */
+vg_status vg_source_set_points_async(vg_source* src, const void* d_xyz, int32_t dtype);
+vg_status vg_source_destroy(vg_source* src);
+
+/* ---- factor batches (Sec. III-C, Implementation) ----------------------- */
+
+/* A batch of F factors; factor f matches src[f] into tgt[f].
+ * target_viewpoints: F x 3 (host) sensor positions in each target frame, used
+ * only with surface_validation (NULL = origin).  Every voxel map in a batch must
+ * have the same number of levels L.  opts may be NULL (defaults). */
+vg_status vg_create_factor_batch(vg_context* ctx, int64_t F, vg_source* const* src,
+                                 vg_voxelmap* const* tgt, const double* target_viewpoints,
+                                 const vg_batch_options* opts, vg_batch** out);
+/* Shape of a batch: total source points, number of work tiles, and the launch
+ * shape in use (block threads, tile points, persistent workgroups). */
+vg_status vg_batch_info(const vg_batch* batch, int64_t* total_points, int64_t* n_tiles,
+                        int32_t* block_threads, int32_t* tile_points, int32_t* grid_blocks);
+vg_status vg_batch_destroy(vg_batch* batch);
+
+/* Linearize every factor at its pose (host arrays): poses F x 12 in; e F,
+ * H F x 36, b F x 6 out; inliers F x L (number of points with a voxel at each
+ * level) or NULL.  One upload and one download per call; synchronous. */
+vg_status vg_linearize(vg_batch* batch, const double* poses, double* e, double* H, double* b,
+                       int64_t* inliers);
+/* Error only, with correspondences and W recomputed at the given poses. */
+vg_status vg_evaluate(vg_batch* batch, const double* poses, double* e);
+
+/* Stream-ordered variants on device pointers (no host synchronization).
+ * d_poses: F x 12 FP64.  d_out: F x 43 FP64 rows [e, H (36), b (6)];
+ * d_inliers: F x L int64 or NULL.  d_e: F FP64. */
+vg_status vg_linearize_async(vg_batch* batch, const double* d_poses, double* d_out, int64_t* d_inliers);
+vg_status vg_evaluate_async(vg_batch* batch, const double* d_poses, double* d_e);
+
+/* Exact gradient of e (W recomputed, not frozen; correspondences held at the
+ * given poses), scaled by d_grad_e (F).  d_jr: F x 36 FP64 right Jacobians
+ * J_r(xi) to apply (grad_xi = J_r^T de/dxi') or NULL for the plain tangent
+ * gradient at T.  d_grad_xi: F x 6 FP64.  d_grad_points: per-point gradient of
+ * every source of the batch in caller order, sources concatenated in order of
+ * first use (n_total x 3; dtype 0 = float32, 1 = float64), or NULL.  A source
+ * used by several factors receives the sum of their gradients. */
+vg_status vg_backward_async(vg_batch* batch, const double* d_poses, const double* d_grad_e,
+                            const double* d_jr, double* d_grad_xi, void* d_grad_points,
+                            int32_t points_dtype);
+
+/* T = T0 Exp(xi) for F poses (device FP64: d_T0 F x 12, d_xi F x 6, d_T F x 12),
+ * and the SE(3) right Jacobian J_r(xi) (F x 36) when d_jr is not NULL. */
+vg_status vg_se3_retract_async(vg_context* ctx, int64_t F, const double* d_T0, const double* d_xi,
+                               double* d_T, double* d_jr);
+
+/* Levenberg-Marquardt, device resident, FP64 6x6 solves (Sec. V-A cites
+ * Levenberg's method): each iteration linearizes at T, solves
+ * (H + lambda diag(H)) delta = -b by Cholesky, evaluates T Exp(delta), accepts
+ * it if e decreases (lambda /= 10) and otherwise keeps T (lambda *= 10).
+ * poses_in/poses_out F x 12, accepted F x iters (may be NULL), e_hist F x iters
+ * (e at each linearization, may be NULL).  One upload and one download. */
+vg_status vg_lm_run(vg_batch* batch, const double* poses_in, int32_t iters, double lambda0,
+                    double* poses_out, int32_t* accepted, double* e_hist);
+
+/* Correspondences of one factor at a pose (host), for parity checks: keys
+ * n x L x 3 absolute voxel coordinates of the transformed points, found n x L
+ * (1 = voxel exists, 0 = none, -1 = point discarded by surface validation),
+ * both in caller order.  Uses the batch's precision mode. */
+vg_status vg_correspondences(vg_batch* batch, const double* pose, int64_t factor, int64_t* keys,
+                             int32_t* found);
+
+/* Autotune the launch shape of a batch at representative poses (host F x 12):
+ * every candidate (block threads x tile points x workgroups per CU) is timed
+ * with HIP events over `reps` launches of the tile kernel and reduction; the
+ * fastest is kept for this batch and, when the batch was created with a
+ * tune_cache path, appended to that file under a key made of the device name
+ * and the batch signature (precision, F, total points, levels, validation).
+ * chosen (may be NULL) receives {block_threads, tile_points, blocks_per_cu}. */
+vg_status vg_batch_tune(vg_batch* batch, const double* poses, int32_t reps, int32_t* chosen);
+
+/* Time the batched kernels on the context stream with HIP events: reps
+ * launches of the tile kernel and of the factor reduction at device-resident
+ * poses (host poses are uploaded once first).  ms[0] = average tile-kernel
+ * time, ms[1] = average reduction time, ms[2] = average whole-call time of
+ * vg_linearize (upload, kernels, download, synchronization). */
+vg_status vg_batch_time_kernels(vg_batch* batch, const double* poses, int32_t reps, float* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VGICP_H */

@@ -1,0 +1,1053 @@
+// C ABI of the VGICP library: validation, handle lifetime, batch scheduling
+// (tile list, plain per-factor loop, batched launch, captured hipGraph),
+// Levenberg-Marquardt driver and the launch-shape autotuner.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+
+#include "vg_internal.h"
+
+namespace {
+
+constexpr uint32_t kCtxMagic = 0xC0FFEE01u;
+constexpr uint32_t kMapMagic = 0x3A900001u;
+constexpr uint32_t kSrcMagic = 0x50CE0001u;
+constexpr uint32_t kBatMagic = 0xBA7C0001u;
+
+thread_local std::string g_err;
+
+bool finite_all(const double* p, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// Leading principal minors of [a b c; b d e; c e f] all positive.
+bool spd6(const double* c) {
+    const double a = c[0], b = c[1], cc = c[2], d = c[3], e = c[4], f = c[5];
+    if (!(a > 0.0)) return false;
+    const double m2 = a * d - b * b;
+    if (!(m2 > 0.0)) return false;
+    const double det = a * (d * f - e * e) - b * (b * f - cc * e) + cc * (b * e - cc * d);
+    return det > 0.0;
+}
+
+bool is_pow2(double r) {
+    int ex = 0;
+    const double m = std::frexp(r, &ex);
+    return m == 0.5;
+}
+
+vg_status invalid(const std::string& msg) {
+    vg::set_error(msg);
+    return VG_ERR_INVALID_ARG;
+}
+
+vg_status state_err(const std::string& msg) {
+    vg::set_error(msg);
+    return VG_ERR_STATE;
+}
+
+bool ctx_ok(const vg_context* c) { return c != nullptr && c->magic == kCtxMagic; }
+bool map_ok(const vg_voxelmap* m) { return m != nullptr && m->magic == kMapMagic; }
+bool src_ok(const vg_source* s) { return s != nullptr && s->magic == kSrcMagic; }
+bool bat_ok(const vg_batch* b) { return b != nullptr && b->magic == kBatMagic; }
+
+// Poses: finite, R orthonormal to 1e-6, det(R) > 0.
+vg_status check_poses(const double* poses, int64_t F) {
+    if (poses == nullptr) return invalid("poses is NULL");
+    for (int64_t f = 0; f < F; ++f) {
+        const double* p = poses + 12 * f;
+        if (!finite_all(p, 12)) return invalid("pose " + std::to_string(f) + " is not finite");
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < 3; ++k) s += p[3 * k + i] * p[3 * k + j];
+                if (std::fabs(s - (i == j ? 1.0 : 0.0)) > 1e-6)
+                    return invalid("pose " + std::to_string(f) + " rotation is not orthonormal");
+            }
+        const double det = p[0] * (p[4] * p[8] - p[5] * p[7]) - p[1] * (p[3] * p[8] - p[5] * p[6]) +
+                           p[2] * (p[3] * p[7] - p[4] * p[6]);
+        if (det <= 0.0) return invalid("pose " + std::to_string(f) + " rotation has det <= 0");
+    }
+    return VG_OK;
+}
+
+template <typename T>
+vg_status dev_alloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * count);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        vg::set_error(std::string("hipMalloc failed: ") + hipGetErrorString(e));
+        return VG_ERR_OOM;
+    }
+    return VG_OK;
+}
+
+template <typename T>
+vg_status host_alloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipHostMalloc((void**)p, sizeof(T) * count, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        vg::set_error(std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
+        return VG_ERR_OOM;
+    }
+    return VG_OK;
+}
+
+#define VG_TRY(x)                          \
+    do {                                   \
+        vg_status _s = (x);                \
+        if (_s != VG_OK) return _s;        \
+    } while (0)
+
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+void hfree(void* p) {
+    if (p) (void)hipHostFree(p);
+}
+
+}  // namespace
+
+namespace vg {
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+vg_status hip_fail(hipError_t e, const char* what) {
+    (void)hipGetLastError();
+    g_err = std::string("HIP error in ") + what + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? VG_ERR_OOM : VG_ERR_HIP;
+}
+
+}  // namespace vg
+
+using namespace vg;
+
+// ============================================================================ context
+
+extern "C" const char* vg_last_error(void) { return g_err.c_str(); }
+
+extern "C" int32_t vg_version(void) { return 10000; }
+
+extern "C" vg_status vg_context_create(int32_t device, void* hip_stream, vg_context** out) {
+    g_err.clear();
+    if (out == nullptr) return invalid("out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) {
+        (void)hipGetLastError();
+        set_error(std::string("no HIP device available") + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : ""));
+        return VG_ERR_HIP;
+    }
+    if (device < 0 || device >= count) return invalid("device index out of range");
+    VG_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    VG_HIP(hipGetDeviceProperties(&prop, device));
+    std::string arch = prop.gcnArchName;
+    if (arch.rfind("gfx950", 0) != 0) {
+        set_error("device " + std::to_string(device) + " is " + arch + "; this library is built for gfx950 only");
+        return VG_ERR_HIP;
+    }
+    auto* c = new vg_context();
+    c->device = device;
+    c->num_cu = prop.multiProcessorCount;
+    c->arch = arch;
+    c->name = prop.name;
+    if (hip_stream != nullptr) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete c;
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        }
+        c->own_stream = true;
+    }
+    c->magic = kCtxMagic;
+    *out = c;
+    return VG_OK;
+}
+
+extern "C" vg_status vg_context_destroy(vg_context* ctx) {
+    g_err.clear();
+    if (!ctx_ok(ctx)) return state_err("invalid context");
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    ctx->magic = 0;
+    delete ctx;
+    return VG_OK;
+}
+
+// ============================================================================ voxel maps
+
+extern "C" vg_status vg_build_voxelmap(vg_context* ctx, const double* xyz, const double* cov, int64_t n,
+                                       const double* resolutions, int32_t L, vg_voxelmap** out) {
+    g_err.clear();
+    if (!ctx_ok(ctx)) return state_err("invalid context");
+    if (out == nullptr) return invalid("out is NULL");
+    *out = nullptr;
+    if (n < 0) return invalid("n < 0");
+    if (n > 0 && (xyz == nullptr || cov == nullptr)) return invalid("xyz or cov is NULL");
+    if (n >= (int64_t)1 << 31) return invalid("n must be below 2^31");
+    if (L < 1 || L > kMaxLevels) return invalid("L must be in 1..4");
+    if (resolutions == nullptr) return invalid("resolutions is NULL");
+    for (int l = 0; l < L; ++l) {
+        const double r = resolutions[l];
+        if (!(std::isfinite(r) && r > 0.0 && is_pow2(r))) return invalid("each resolution must be a positive power of two");
+        if (l > 0 && !(r > resolutions[l - 1])) return invalid("resolutions must be strictly ascending");
+    }
+    if (n > 0 && !finite_all(xyz, 3 * n)) return invalid("xyz has non-finite values");
+    if (n > 0 && !finite_all(cov, 6 * n)) return invalid("cov has non-finite values");
+    for (int64_t i = 0; i < n; ++i)
+        if (!spd6(cov + 6 * i)) {
+            set_error("covariance of point " + std::to_string(i) + " is not SPD");
+            return VG_ERR_NOT_SPD;
+        }
+    VG_HIP(hipSetDevice(ctx->device));
+    auto* m = new vg_voxelmap();
+    m->ctx = ctx;
+    m->L = L;
+    const double rmax = resolutions[L - 1];
+    for (int a = 0; a < 3; ++a) m->origin[a] = (n > 0) ? rmax * std::nearbyint(xyz[a] / rmax) : 0.0;
+    double *d_xyz = nullptr, *d_cov = nullptr;
+    uint64_t* d_keys = nullptr;
+    int32_t* d_idx = nullptr;
+    int32_t* d_flag = nullptr;
+    void* d_tmp = nullptr;
+    const size_t tmp_bytes = build_level_scratch_bytes(n);
+    vg_status st = VG_OK;
+    do {
+        if ((st = dev_alloc(&d_xyz, 3 * n)) != VG_OK) break;
+        if ((st = dev_alloc(&d_cov, 6 * n)) != VG_OK) break;
+        if ((st = dev_alloc(&d_keys, 3 * n + 64)) != VG_OK) break;
+        if ((st = dev_alloc(&d_idx, 4 * n + 64)) != VG_OK) break;
+        if ((st = dev_alloc(&d_flag, 64)) != VG_OK) break;
+        if ((st = dev_alloc((char**)&d_tmp, tmp_bytes)) != VG_OK) break;
+        hipError_t e = hipSuccess;
+        if (n > 0) {
+            e = hipMemcpyAsync(d_xyz, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, ctx->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d_cov, cov, sizeof(double) * 6 * n, hipMemcpyHostToDevice, ctx->stream);
+        }
+        if (e != hipSuccess) {
+            st = hip_fail(e, "voxelmap upload");
+            break;
+        }
+        for (int l = 0; l < L && st == VG_OK; ++l)
+            st = build_level(ctx, d_xyz, d_cov, n, resolutions[l], m->origin, &m->lv[l], d_keys, d_idx, d_tmp,
+                             tmp_bytes, d_flag);
+    } while (0);
+    dfree(d_xyz);
+    dfree(d_cov);
+    dfree(d_keys);
+    dfree(d_idx);
+    dfree(d_flag);
+    dfree(d_tmp);
+    if (st != VG_OK) {
+        for (int l = 0; l < kMaxLevels; ++l) free_level(&m->lv[l]);
+        delete m;
+        return st;
+    }
+    m->magic = kMapMagic;
+    *out = m;
+    return VG_OK;
+}
+
+extern "C" vg_status vg_voxelmap_info(const vg_voxelmap* map, int32_t level, int64_t* n_voxels, int64_t* capacity) {
+    g_err.clear();
+    if (!map_ok(map)) return state_err("invalid voxel map");
+    if (level < 0 || level >= map->L) return invalid("level out of range");
+    if (n_voxels) *n_voxels = map->lv[level].V;
+    if (capacity) *capacity = (int64_t)1 << map->lv[level].log2cap;
+    return VG_OK;
+}
+
+extern "C" vg_status vg_voxelmap_export(const vg_voxelmap* map, int32_t level, int64_t* n_voxels, int64_t* keys,
+                                        double* means, double* covs, int64_t* counts) {
+    g_err.clear();
+    if (!map_ok(map)) return state_err("invalid voxel map");
+    if (level < 0 || level >= map->L) return invalid("level out of range");
+    if (n_voxels == nullptr) return invalid("n_voxels is NULL");
+    const int64_t V = map->lv[level].V;
+    if (*n_voxels < V) {
+        *n_voxels = V;
+        return invalid("output capacity too small");
+    }
+    *n_voxels = V;
+    VG_HIP(hipSetDevice(map->ctx->device));
+    return export_level(map->ctx, map->lv[level], keys, means, covs, counts);
+}
+
+extern "C" vg_status vg_voxelmap_destroy(vg_voxelmap* map) {
+    g_err.clear();
+    if (!map_ok(map)) return state_err("invalid voxel map");
+    if (map->users > 0) return state_err("voxel map is used by a live batch");
+    (void)hipSetDevice(map->ctx->device);
+    (void)hipStreamSynchronize(map->ctx->stream);
+    for (int l = 0; l < kMaxLevels; ++l) free_level(&map->lv[l]);
+    map->magic = 0;
+    delete map;
+    return VG_OK;
+}
+
+// ============================================================================ sources
+
+static void free_source(vg_source* s) {
+    dfree(s->dxyz);
+    dfree(s->cov);
+    dfree(s->nrm);
+    dfree(s->anchor);
+    dfree(s->axyz);
+    dfree(s->xyz64);
+    dfree(s->cov64);
+    dfree(s->nrm64);
+    dfree(s->perm);
+}
+
+extern "C" vg_status vg_create_source(vg_context* ctx, const double* xyz, const double* cov, const double* normals,
+                                      int64_t n, vg_source** out) {
+    g_err.clear();
+    if (!ctx_ok(ctx)) return state_err("invalid context");
+    if (out == nullptr) return invalid("out is NULL");
+    *out = nullptr;
+    if (n < 0) return invalid("n < 0");
+    if (n >= (int64_t)1 << 31) return invalid("n must be below 2^31");
+    if (n > 0 && (xyz == nullptr || cov == nullptr)) return invalid("xyz or cov is NULL");
+    if (n > 0 && !finite_all(xyz, 3 * n)) return invalid("xyz has non-finite values");
+    if (n > 0 && !finite_all(cov, 6 * n)) return invalid("cov has non-finite values");
+    if (n > 0 && normals && !finite_all(normals, 3 * n)) return invalid("normals have non-finite values");
+    for (int64_t i = 0; i < n; ++i)
+        if (!spd6(cov + 6 * i)) {
+            set_error("covariance of point " + std::to_string(i) + " is not SPD");
+            return VG_ERR_NOT_SPD;
+        }
+    VG_HIP(hipSetDevice(ctx->device));
+    auto* s = new vg_source();
+    s->ctx = ctx;
+    s->n = n;
+    s->n_pad = ((n + kChunk - 1) / kChunk) * kChunk;
+    s->n_chunks = s->n_pad / kChunk;
+    s->has_normals = normals != nullptr;
+    for (int a = 0; a < 3; ++a) s->origin[a] = (n > 0) ? std::nearbyint(xyz[a]) : 0.0;
+    const int64_t np = s->n_pad;
+    double *d_xyz = nullptr, *d_cov = nullptr, *d_nrm = nullptr;
+    vg_status st = VG_OK;
+    do {
+        if ((st = dev_alloc(&s->dxyz, 3 * np)) != VG_OK) break;
+        if ((st = dev_alloc(&s->cov, 6 * np)) != VG_OK) break;
+        if ((st = dev_alloc(&s->anchor, 3 * s->n_chunks)) != VG_OK) break;
+        if ((st = dev_alloc(&s->axyz, 3 * np)) != VG_OK) break;
+        if ((st = dev_alloc(&s->xyz64, 3 * np)) != VG_OK) break;
+        if ((st = dev_alloc(&s->cov64, 6 * np)) != VG_OK) break;
+        if ((st = dev_alloc(&s->perm, np)) != VG_OK) break;
+        if (normals) {
+            if ((st = dev_alloc(&s->nrm, 3 * np)) != VG_OK) break;
+            if ((st = dev_alloc(&s->nrm64, 3 * np)) != VG_OK) break;
+        }
+        if (n == 0) break;
+        if ((st = dev_alloc(&d_xyz, 3 * n)) != VG_OK) break;
+        if ((st = dev_alloc(&d_cov, 6 * n)) != VG_OK) break;
+        if (normals && (st = dev_alloc(&d_nrm, 3 * n)) != VG_OK) break;
+        hipError_t e = hipMemcpyAsync(d_xyz, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_cov, cov, sizeof(double) * 6 * n, hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess && normals)
+            e = hipMemcpyAsync(d_nrm, normals, sizeof(double) * 3 * n, hipMemcpyHostToDevice, ctx->stream);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "source upload");
+            break;
+        }
+        st = layout_source(ctx, s, d_xyz, d_cov, d_nrm);
+    } while (0);
+    dfree(d_xyz);
+    dfree(d_cov);
+    dfree(d_nrm);
+    if (st != VG_OK) {
+        free_source(s);
+        delete s;
+        return st;
+    }
+    s->magic = kSrcMagic;
+    *out = s;
+    return VG_OK;
+}
+
+extern "C" vg_status vg_source_set_points_async(vg_source* src, const void* d_xyz, int32_t dtype) {
+    g_err.clear();
+    if (!src_ok(src)) return state_err("invalid source");
+    if (dtype != 0 && dtype != 1) return invalid("dtype must be 0 (float32) or 1 (float64)");
+    if (src->n > 0 && d_xyz == nullptr) return invalid("d_xyz is NULL");
+    VG_HIP(hipSetDevice(src->ctx->device));
+    return set_source_points(src->ctx, src, d_xyz, dtype);
+}
+
+extern "C" vg_status vg_source_destroy(vg_source* src) {
+    g_err.clear();
+    if (!src_ok(src)) return state_err("invalid source");
+    if (src->users > 0) return state_err("source is used by a live batch");
+    (void)hipSetDevice(src->ctx->device);
+    (void)hipStreamSynchronize(src->ctx->stream);
+    free_source(src);
+    src->magic = 0;
+    delete src;
+    return VG_OK;
+}
+
+// ============================================================================ batches
+
+namespace {
+
+void fill_factor(vg_batch* b, int64_t f, const double* viewpoints) {
+    const vg_source* s = b->src[f];
+    const vg_voxelmap* m = b->tgt[f];
+    FactorDesc d{};
+    d.dxyz = s->dxyz;
+    d.cov = s->cov;
+    d.nrm = s->nrm;
+    d.anchor = s->anchor;
+    d.axyz = s->axyz;
+    d.xyz64 = s->xyz64;
+    d.cov64 = s->cov64;
+    d.nrm64 = s->nrm64;
+    d.perm = s->perm;
+    d.n = s->n;
+    d.n_pad = s->n_pad;
+    d.L = m->L;
+    for (int a = 0; a < 3; ++a) {
+        d.src_origin[a] = s->origin[a];
+        d.viewpoint[a] = viewpoints ? viewpoints[3 * f + a] : 0.0;
+    }
+    const double rmax = m->lv[m->L - 1].r;
+    for (int l = 0; l < m->L; ++l) {
+        const Level& lv = m->lv[l];
+        LevelDesc& q = d.lv[l];
+        q.slots = lv.slots;
+        q.rec32 = lv.rec32;
+        q.recN = lv.recN;
+        q.rec64 = lv.rec64;
+        q.log2cap = lv.log2cap;
+        q.scale = (int32_t)std::llround(rmax / lv.r);
+        q.r = (float)lv.r;
+        q.inv_r = (float)(1.0 / lv.r);
+        q.r64 = lv.r;
+        q.inv_r64 = 1.0 / lv.r;
+        for (int a = 0; a < 3; ++a) q.K0[a] = lv.K0[a];
+    }
+    b->h_fac[f] = d;
+}
+
+void build_tiles(vg_batch* b) {
+    const int tc = std::max(1, b->tile_points / kChunk);
+    b->h_tiles.clear();
+    b->h_tile_first.assign(b->F + 1, 0);
+    for (int64_t f = 0; f < b->F; ++f) {
+        b->h_tile_first[f] = (int32_t)b->h_tiles.size();
+        const int64_t nch = b->src[f]->n_chunks;
+        for (int64_t c = 0; c < nch; c += tc) {
+            Tile t{};
+            t.factor = (int32_t)f;
+            t.chunk0 = (int32_t)c;
+            t.nchunks = (int32_t)std::min<int64_t>(tc, nch - c);
+            b->h_tiles.push_back(t);
+        }
+    }
+    b->h_tile_first[b->F] = (int32_t)b->h_tiles.size();
+}
+
+void free_graph(vg_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+vg_status upload_schedule(vg_batch* b) {
+    hipStream_t st = b->ctx->stream;
+    dfree(b->d_tiles);
+    dfree(b->d_tile_first);
+    dfree(b->d_partials);
+    b->d_tiles = nullptr;
+    b->d_tile_first = nullptr;
+    b->d_partials = nullptr;
+    const size_t nt = b->h_tiles.size();
+    VG_TRY(dev_alloc(&b->d_tiles, nt));
+    VG_TRY(dev_alloc(&b->d_tile_first, b->F + 1));
+    VG_TRY(dev_alloc(&b->d_partials, (size_t)kRow * std::max<size_t>(nt, 1)));
+    if (nt) VG_HIP(hipMemcpyAsync(b->d_tiles, b->h_tiles.data(), sizeof(Tile) * nt, hipMemcpyHostToDevice, st));
+    VG_HIP(hipMemcpyAsync(b->d_tile_first, b->h_tile_first.data(), sizeof(int32_t) * (b->F + 1),
+                          hipMemcpyHostToDevice, st));
+    const int64_t want = (int64_t)b->ctx->num_cu * b->blocks_per_cu;
+    b->grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)nt));
+    VG_HIP(hipStreamSynchronize(st));
+    free_graph(b);
+    return VG_OK;
+}
+
+int default_blocks_per_cu(int block) { return std::max(1, 2048 / block); }
+
+std::string tune_key(const vg_batch* b) {
+    std::ostringstream k;
+    k << b->ctx->name << "|" << b->ctx->arch << "|p" << b->opt.precision << "|F" << b->F << "|N" << b->total_points
+      << "|L" << b->L << "|v" << b->opt.surface_validation;
+    return k.str();
+}
+
+bool tune_lookup(const vg_batch* b, int* block, int* tile, int* bpc) {
+    if (b->opt.tune_cache == nullptr) return false;
+    std::ifstream in(b->opt.tune_cache);
+    if (!in) return false;
+    const std::string key = "\"key\": \"" + tune_key(b) + "\"";
+    std::string line;
+    bool found = false;
+    while (std::getline(in, line)) {
+        if (line.find(key) == std::string::npos) continue;
+        int bl = 0, tp = 0, bc = 0;
+        const char* p1 = std::strstr(line.c_str(), "\"block\": ");
+        const char* p2 = std::strstr(line.c_str(), "\"tile_points\": ");
+        const char* p3 = std::strstr(line.c_str(), "\"blocks_per_cu\": ");
+        if (p1 && p2 && p3 && std::sscanf(p1 + 9, "%d", &bl) == 1 && std::sscanf(p2 + 15, "%d", &tp) == 1 &&
+            std::sscanf(p3 + 17, "%d", &bc) == 1) {
+            *block = bl;
+            *tile = tp;
+            *bpc = bc;
+            found = true;   // last entry wins
+        }
+    }
+    return found;
+}
+
+bool valid_shape(int block, int tile, int bpc) {
+    return (block == 64 || block == 128 || block == 256 || block == 512) && tile >= kChunk && tile % kChunk == 0 &&
+           tile / kChunk <= kMaxTileChunks && bpc >= 1 && bpc <= 64;
+}
+
+vg_status run_linearize_device(vg_batch* b, const double* d_poses, double* d_out, int64_t* d_inl) {
+    const int32_t nt = (int32_t)b->h_tiles.size();
+    VG_TRY(launch_tiles(b, kLin, d_poses, 0, nt, b->grid, nullptr, nullptr, 0));
+    return launch_reduce(b, kLin, d_poses, 0, (int32_t)b->F, d_out, d_inl, nullptr, nullptr, nullptr);
+}
+
+vg_status run_evaluate_device(vg_batch* b, const double* d_poses, double* d_e) {
+    const int32_t nt = (int32_t)b->h_tiles.size();
+    VG_TRY(launch_tiles(b, kEval, d_poses, 0, nt, b->grid, nullptr, nullptr, 0));
+    return launch_reduce(b, kEval, d_poses, 0, (int32_t)b->F, d_e, nullptr, nullptr, nullptr, nullptr);
+}
+
+// Capture [H2D poses, tile kernel, reduction, D2H results] once; replayed per call.
+vg_status ensure_graph(vg_batch* b) {
+    if (b->exec) return VG_OK;
+    hipStream_t cs = nullptr;
+    VG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipStream_t saved = b->ctx->stream;
+    b->ctx->stream = cs;
+    vg_status st = VG_OK;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        e = hipMemcpyAsync(b->d_poses, b->h_poses, sizeof(double) * 12 * b->F, hipMemcpyHostToDevice, cs);
+        if (e == hipSuccess) st = run_linearize_device(b, b->d_poses, b->d_out, b->d_inliers);
+        if (e == hipSuccess && st == VG_OK)
+            e = hipMemcpyAsync(b->h_out, b->d_out, sizeof(double) * kOutRow * b->F, hipMemcpyDeviceToHost, cs);
+        if (e == hipSuccess && st == VG_OK)
+            e = hipMemcpyAsync(b->h_inliers, b->d_inliers, sizeof(int64_t) * b->L * b->F, hipMemcpyDeviceToHost, cs);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e2;
+        b->graph = g;
+        if (e == hipSuccess && st == VG_OK) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    }
+    b->ctx->stream = saved;
+    (void)hipStreamDestroy(cs);
+    if (st != VG_OK) {
+        free_graph(b);
+        return st;
+    }
+    if (e != hipSuccess) {
+        free_graph(b);
+        return hip_fail(e, "graph capture");
+    }
+    return VG_OK;
+}
+
+// The whole host-side linearize: stage poses, run, fetch results (pinned buffers).
+vg_status linearize_host(vg_batch* b) {
+    hipStream_t st = b->ctx->stream;
+    const int64_t F = b->F;
+    if (b->opt.plain_per_factor) {
+        for (int64_t f = 0; f < F; ++f) {
+            VG_HIP(hipMemcpyAsync(b->d_poses + 12 * f, b->h_poses + 12 * f, sizeof(double) * 12,
+                                  hipMemcpyHostToDevice, st));
+            const int32_t t0 = b->h_tile_first[f], t1 = b->h_tile_first[f + 1];
+            const int grid = std::max(1, std::min(t1 - t0, b->grid));
+            VG_TRY(launch_tiles(b, kLin, b->d_poses, t0, t1, grid, nullptr, nullptr, 0));
+            VG_TRY(launch_reduce(b, kLin, b->d_poses, (int32_t)f, (int32_t)f + 1, b->d_out, b->d_inliers, nullptr,
+                                 nullptr, nullptr));
+            VG_HIP(hipMemcpyAsync(b->h_out + kOutRow * f, b->d_out + kOutRow * f, sizeof(double) * kOutRow,
+                                  hipMemcpyDeviceToHost, st));
+            VG_HIP(hipMemcpyAsync(b->h_inliers + b->L * f, b->d_inliers + b->L * f, sizeof(int64_t) * b->L,
+                                  hipMemcpyDeviceToHost, st));
+            VG_HIP(hipStreamSynchronize(st));
+        }
+        return VG_OK;
+    }
+    if (b->opt.use_graph) {
+        VG_TRY(ensure_graph(b));
+        VG_HIP(hipGraphLaunch(b->exec, st));
+        VG_HIP(hipStreamSynchronize(st));
+        return VG_OK;
+    }
+    VG_HIP(hipMemcpyAsync(b->d_poses, b->h_poses, sizeof(double) * 12 * F, hipMemcpyHostToDevice, st));
+    VG_TRY(run_linearize_device(b, b->d_poses, b->d_out, b->d_inliers));
+    VG_HIP(hipMemcpyAsync(b->h_out, b->d_out, sizeof(double) * kOutRow * F, hipMemcpyDeviceToHost, st));
+    VG_HIP(hipMemcpyAsync(b->h_inliers, b->d_inliers, sizeof(int64_t) * b->L * F, hipMemcpyDeviceToHost, st));
+    VG_HIP(hipStreamSynchronize(st));
+    return VG_OK;
+}
+
+void free_batch(vg_batch* b) {
+    free_graph(b);
+    dfree(b->d_fac);
+    dfree(b->d_tiles);
+    dfree(b->d_tile_first);
+    dfree(b->d_partials);
+    dfree(b->d_counter);
+    dfree(b->d_poses);
+    dfree(b->d_out);
+    dfree(b->d_inliers);
+    dfree(b->d_e);
+    dfree(b->d_lm);
+    hfree(b->h_poses);
+    hfree(b->h_out);
+    hfree(b->h_inliers);
+}
+
+}  // namespace
+
+extern "C" vg_status vg_create_factor_batch(vg_context* ctx, int64_t F, vg_source* const* src,
+                                            vg_voxelmap* const* tgt, const double* target_viewpoints,
+                                            const vg_batch_options* opts, vg_batch** out) {
+    g_err.clear();
+    if (!ctx_ok(ctx)) return state_err("invalid context");
+    if (out == nullptr) return invalid("out is NULL");
+    *out = nullptr;
+    if (F < 1) return invalid("F must be >= 1");
+    if (F >= (int64_t)1 << 30) return invalid("F too large");
+    if (src == nullptr || tgt == nullptr) return invalid("src or tgt is NULL");
+    vg_batch_options o{};
+    if (opts) o = *opts;
+    if (o.precision < 0 || o.precision > 2) return invalid("unknown precision");
+    if (target_viewpoints && !finite_all(target_viewpoints, 3 * F)) return invalid("viewpoints are not finite");
+    int L = -1;
+    for (int64_t f = 0; f < F; ++f) {
+        if (!src_ok(src[f])) return state_err("factor " + std::to_string(f) + ": invalid source");
+        if (!map_ok(tgt[f])) return state_err("factor " + std::to_string(f) + ": invalid voxel map");
+        if (src[f]->ctx != ctx || tgt[f]->ctx != ctx) return state_err("handle from another context");
+        if (L < 0) L = tgt[f]->L;
+        if (tgt[f]->L != L) return invalid("all voxel maps of a batch need the same number of levels");
+        if (o.surface_validation && !src[f]->has_normals)
+            return invalid("surface validation needs sources created with normals");
+        if (src[f]->n_chunks > ((int64_t)1 << 31) / 2) return invalid("source too large");
+    }
+    int block = o.block_threads ? o.block_threads : 256;
+    int tile = o.tile_points ? o.tile_points : 2048;
+    int bpc = o.blocks_per_cu ? o.blocks_per_cu : default_blocks_per_cu(block);
+    if (!valid_shape(block, tile, bpc)) return invalid("invalid launch shape (block 64/128/256/512, tile a multiple of 64 up to 8192)");
+    VG_HIP(hipSetDevice(ctx->device));
+    auto* b = new vg_batch();
+    b->ctx = ctx;
+    b->F = F;
+    b->L = L;
+    b->opt = o;
+    b->opt.tune_cache = nullptr;
+    b->src.assign(src, src + F);
+    b->tgt.assign(tgt, tgt + F);
+    b->h_fac.resize(F);
+    // concatenated point-gradient rows: sources in order of first use
+    std::map<const vg_source*, std::pair<int64_t, int>> seen;
+    int64_t rows = 0;
+    for (int64_t f = 0; f < F; ++f) {
+        auto it = seen.find(src[f]);
+        if (it == seen.end()) {
+            seen[src[f]] = {rows, 1};
+            rows += src[f]->n;
+        } else {
+            it->second.second += 1;
+        }
+        b->total_points += src[f]->n;
+    }
+    b->grad_rows = rows;
+    for (int64_t f = 0; f < F; ++f) {
+        fill_factor(b, f, target_viewpoints);
+        b->h_fac[f].grad_offset = seen[src[f]].first;
+        b->h_fac[f].grad_exclusive = seen[src[f]].second == 1 ? 1 : 0;
+    }
+    b->block = block;
+    b->tile_points = tile;
+    b->blocks_per_cu = bpc;
+    if (opts && opts->tune_cache) {
+        b->opt.tune_cache = strdup(opts->tune_cache);
+        int bl = 0, tp = 0, bc = 0;
+        if (!o.block_threads && !o.tile_points && !o.blocks_per_cu && tune_lookup(b, &bl, &tp, &bc) &&
+            valid_shape(bl, tp, bc)) {
+            b->block = bl;
+            b->tile_points = tp;
+            b->blocks_per_cu = bc;
+        }
+    }
+    build_tiles(b);
+    vg_status st = VG_OK;
+    do {
+        if ((st = dev_alloc(&b->d_fac, F)) != VG_OK) break;
+        if ((st = dev_alloc(&b->d_counter, 64)) != VG_OK) break;
+        if ((st = dev_alloc(&b->d_poses, 12 * F)) != VG_OK) break;
+        if ((st = dev_alloc(&b->d_out, kOutRow * F)) != VG_OK) break;
+        if ((st = dev_alloc(&b->d_inliers, (size_t)L * F)) != VG_OK) break;
+        if ((st = dev_alloc(&b->d_e, F)) != VG_OK) break;
+        if ((st = dev_alloc(&b->d_lm, 32 * F)) != VG_OK) break;
+        if ((st = host_alloc(&b->h_poses, 12 * F)) != VG_OK) break;
+        if ((st = host_alloc(&b->h_out, kOutRow * F)) != VG_OK) break;
+        if ((st = host_alloc(&b->h_inliers, (size_t)L * F)) != VG_OK) break;
+        hipError_t e = hipMemcpyAsync(b->d_fac, b->h_fac.data(), sizeof(FactorDesc) * F, hipMemcpyHostToDevice,
+                                      ctx->stream);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "factor table upload");
+            break;
+        }
+        if ((st = launch_zero(ctx, b->d_counter, 64 * sizeof(uint32_t))) != VG_OK) break;
+        st = upload_schedule(b);
+    } while (0);
+    if (st != VG_OK) {
+        free_batch(b);
+        if (b->opt.tune_cache) free((void*)b->opt.tune_cache);
+        delete b;
+        return st;
+    }
+    for (int64_t f = 0; f < F; ++f) {
+        src[f]->users += 1;
+        tgt[f]->users += 1;
+    }
+    b->magic = kBatMagic;
+    *out = b;
+    return VG_OK;
+}
+
+extern "C" vg_status vg_batch_info(const vg_batch* b, int64_t* total_points, int64_t* n_tiles, int32_t* block_threads,
+                                   int32_t* tile_points, int32_t* grid_blocks) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    if (total_points) *total_points = b->total_points;
+    if (n_tiles) *n_tiles = (int64_t)b->h_tiles.size();
+    if (block_threads) *block_threads = b->block;
+    if (tile_points) *tile_points = b->tile_points;
+    if (grid_blocks) *grid_blocks = b->grid;
+    return VG_OK;
+}
+
+extern "C" vg_status vg_batch_destroy(vg_batch* b) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    (void)hipSetDevice(b->ctx->device);
+    (void)hipStreamSynchronize(b->ctx->stream);
+    for (int64_t f = 0; f < b->F; ++f) {
+        b->src[f]->users -= 1;
+        b->tgt[f]->users -= 1;
+    }
+    free_batch(b);
+    if (b->opt.tune_cache) free((void*)b->opt.tune_cache);
+    b->magic = 0;
+    delete b;
+    return VG_OK;
+}
+
+extern "C" vg_status vg_linearize(vg_batch* b, const double* poses, double* e, double* H, double* bv,
+                                  int64_t* inliers) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    if (e == nullptr || H == nullptr || bv == nullptr) return invalid("e, H or b is NULL");
+    VG_TRY(check_poses(poses, b->F));
+    VG_HIP(hipSetDevice(b->ctx->device));
+    std::memcpy(b->h_poses, poses, sizeof(double) * 12 * b->F);
+    VG_TRY(linearize_host(b));
+    for (int64_t f = 0; f < b->F; ++f) {
+        const double* r = b->h_out + kOutRow * f;
+        e[f] = r[0];
+        std::memcpy(H + 36 * f, r + 1, sizeof(double) * 36);
+        std::memcpy(bv + 6 * f, r + 37, sizeof(double) * 6);
+    }
+    if (inliers) std::memcpy(inliers, b->h_inliers, sizeof(int64_t) * b->L * b->F);
+    return VG_OK;
+}
+
+extern "C" vg_status vg_evaluate(vg_batch* b, const double* poses, double* e) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    if (e == nullptr) return invalid("e is NULL");
+    VG_TRY(check_poses(poses, b->F));
+    VG_HIP(hipSetDevice(b->ctx->device));
+    hipStream_t st = b->ctx->stream;
+    std::memcpy(b->h_poses, poses, sizeof(double) * 12 * b->F);
+    VG_HIP(hipMemcpyAsync(b->d_poses, b->h_poses, sizeof(double) * 12 * b->F, hipMemcpyHostToDevice, st));
+    VG_TRY(run_evaluate_device(b, b->d_poses, b->d_e));
+    VG_HIP(hipMemcpyAsync(b->h_out, b->d_e, sizeof(double) * b->F, hipMemcpyDeviceToHost, st));
+    VG_HIP(hipStreamSynchronize(st));
+    std::memcpy(e, b->h_out, sizeof(double) * b->F);
+    return VG_OK;
+}
+
+extern "C" vg_status vg_linearize_async(vg_batch* b, const double* d_poses, double* d_out, int64_t* d_inliers) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    if (d_poses == nullptr || d_out == nullptr) return invalid("d_poses or d_out is NULL");
+    VG_HIP(hipSetDevice(b->ctx->device));
+    return run_linearize_device(b, d_poses, d_out, d_inliers);
+}
+
+extern "C" vg_status vg_evaluate_async(vg_batch* b, const double* d_poses, double* d_e) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    if (d_poses == nullptr || d_e == nullptr) return invalid("d_poses or d_e is NULL");
+    VG_HIP(hipSetDevice(b->ctx->device));
+    return run_evaluate_device(b, d_poses, d_e);
+}
+
+extern "C" vg_status vg_backward_async(vg_batch* b, const double* d_poses, const double* d_grad_e, const double* d_jr,
+                                       double* d_grad_xi, void* d_grad_points, int32_t points_dtype) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    if (d_poses == nullptr || d_grad_e == nullptr || d_grad_xi == nullptr)
+        return invalid("d_poses, d_grad_e or d_grad_xi is NULL");
+    if (points_dtype != 0 && points_dtype != 1) return invalid("points_dtype must be 0 or 1");
+    VG_HIP(hipSetDevice(b->ctx->device));
+    if (d_grad_points)
+        VG_TRY(launch_zero(b->ctx, d_grad_points, (size_t)b->grad_rows * 3 * (points_dtype ? 8 : 4)));
+    const int32_t nt = (int32_t)b->h_tiles.size();
+    VG_TRY(launch_tiles(b, kBwd, d_poses, 0, nt, b->grid, d_grad_e, d_grad_points, points_dtype));
+    return launch_reduce(b, kBwd, d_poses, 0, (int32_t)b->F, nullptr, nullptr, d_grad_e, d_jr, d_grad_xi);
+}
+
+extern "C" vg_status vg_se3_retract_async(vg_context* ctx, int64_t F, const double* d_T0, const double* d_xi,
+                                          double* d_T, double* d_jr) {
+    g_err.clear();
+    if (!ctx_ok(ctx)) return state_err("invalid context");
+    if (F < 0) return invalid("F < 0");
+    if (F > 0 && (d_T0 == nullptr || d_xi == nullptr || d_T == nullptr)) return invalid("NULL pointer");
+    VG_HIP(hipSetDevice(ctx->device));
+    return launch_se3_retract(ctx, F, d_T0, d_xi, d_T, d_jr);
+}
+
+extern "C" vg_status vg_lm_run(vg_batch* b, const double* poses_in, int32_t iters, double lambda0, double* poses_out,
+                               int32_t* accepted, double* e_hist) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    if (poses_out == nullptr) return invalid("poses_out is NULL");
+    if (iters < 0 || iters > 10000) return invalid("iters out of range");
+    if (!(std::isfinite(lambda0) && lambda0 > 0)) return invalid("lambda0 must be positive");
+    VG_TRY(check_poses(poses_in, b->F));
+    VG_HIP(hipSetDevice(b->ctx->device));
+    hipStream_t st = b->ctx->stream;
+    const int64_t F = b->F;
+    double* state = b->d_lm;                 // 4 per factor
+    double* cand = b->d_lm + 4 * F;          // 12 per factor
+    double* e_new = b->d_lm + 16 * F;        // 1 per factor
+    int32_t* d_acc = nullptr;
+    double* d_eh = nullptr;
+    VG_TRY(dev_alloc(&d_acc, (size_t)F * std::max(iters, 1)));
+    vg_status rc = dev_alloc(&d_eh, (size_t)F * std::max(iters, 1));
+    if (rc != VG_OK) {
+        dfree(d_acc);
+        return rc;
+    }
+    do {
+        std::memcpy(b->h_poses, poses_in, sizeof(double) * 12 * F);
+        hipError_t e = hipMemcpyAsync(b->d_poses, b->h_poses, sizeof(double) * 12 * F, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "pose upload");
+            break;
+        }
+        if ((rc = launch_lm_init(b, state, lambda0)) != VG_OK) break;
+        for (int32_t it = 0; it < iters && rc == VG_OK; ++it) {
+            if ((rc = run_linearize_device(b, b->d_poses, b->d_out, nullptr)) != VG_OK) break;
+            if ((rc = launch_lm_propose(b, b->d_out, state, b->d_poses, cand)) != VG_OK) break;
+            if ((rc = run_evaluate_device(b, cand, e_new)) != VG_OK) break;
+            rc = launch_lm_accept(b, e_new, state, b->d_poses, cand, d_acc, d_eh, it, iters);
+        }
+        if (rc != VG_OK) break;
+        std::vector<int32_t> ha((size_t)F * std::max(iters, 1));
+        std::vector<double> he((size_t)F * std::max(iters, 1));
+        e = hipMemcpyAsync(b->h_poses, b->d_poses, sizeof(double) * 12 * F, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && iters > 0)
+            e = hipMemcpyAsync(ha.data(), d_acc, sizeof(int32_t) * F * iters, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && iters > 0)
+            e = hipMemcpyAsync(he.data(), d_eh, sizeof(double) * F * iters, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "LM download");
+            break;
+        }
+        std::memcpy(poses_out, b->h_poses, sizeof(double) * 12 * F);
+        if (accepted && iters > 0) std::memcpy(accepted, ha.data(), sizeof(int32_t) * F * iters);
+        if (e_hist && iters > 0) std::memcpy(e_hist, he.data(), sizeof(double) * F * iters);
+    } while (0);
+    dfree(d_acc);
+    dfree(d_eh);
+    return rc;
+}
+
+extern "C" vg_status vg_correspondences(vg_batch* b, const double* pose, int64_t factor, int64_t* keys,
+                                        int32_t* found) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    if (factor < 0 || factor >= b->F) return invalid("factor out of range");
+    if (keys == nullptr || found == nullptr) return invalid("keys or found is NULL");
+    VG_TRY(check_poses(pose, 1));
+    VG_HIP(hipSetDevice(b->ctx->device));
+    hipStream_t st = b->ctx->stream;
+    const int64_t n = b->src[factor]->n, L = b->L;
+    if (n == 0) return VG_OK;
+    double* d_pose = nullptr;
+    int64_t* d_keys = nullptr;
+    int32_t* d_found = nullptr;
+    vg_status rc = VG_OK;
+    do {
+        if ((rc = dev_alloc(&d_pose, 12)) != VG_OK) break;
+        if ((rc = dev_alloc(&d_keys, (size_t)n * L * 3)) != VG_OK) break;
+        if ((rc = dev_alloc(&d_found, (size_t)n * L)) != VG_OK) break;
+        hipError_t e = hipMemcpyAsync(d_pose, pose, sizeof(double) * 12, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "pose upload");
+            break;
+        }
+        if ((rc = launch_correspondences(b, d_pose, factor, d_keys, d_found)) != VG_OK) break;
+        e = hipMemcpyAsync(keys, d_keys, sizeof(int64_t) * n * L * 3, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(found, d_found, sizeof(int32_t) * n * L, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = hip_fail(e, "correspondence download");
+    } while (0);
+    dfree(d_pose);
+    dfree(d_keys);
+    dfree(d_found);
+    return rc;
+}
+
+namespace {
+
+// Average device time of the tile kernel and the reduction over `reps` launches.
+vg_status time_device(vg_batch* b, int reps, float* ms_tiles, float* ms_reduce) {
+    hipStream_t st = b->ctx->stream;
+    const int32_t nt = (int32_t)b->h_tiles.size();
+    std::vector<hipEvent_t> ev(3 * reps);
+    for (auto& x : ev) VG_HIP(hipEventCreate(&x));
+    vg_status rc = run_linearize_device(b, b->d_poses, b->d_out, b->d_inliers);   // warm-up
+    for (int r = 0; r < reps && rc == VG_OK; ++r) {
+        (void)hipEventRecord(ev[3 * r], st);
+        rc = launch_tiles(b, kLin, b->d_poses, 0, nt, b->grid, nullptr, nullptr, 0);
+        (void)hipEventRecord(ev[3 * r + 1], st);
+        if (rc == VG_OK)
+            rc = launch_reduce(b, kLin, b->d_poses, 0, (int32_t)b->F, b->d_out, b->d_inliers, nullptr, nullptr,
+                               nullptr);
+        (void)hipEventRecord(ev[3 * r + 2], st);
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    float t1 = 0.f, t2 = 0.f;
+    if (rc == VG_OK && e == hipSuccess) {
+        for (int r = 0; r < reps; ++r) {
+            float a = 0.f, c = 0.f;
+            (void)hipEventElapsedTime(&a, ev[3 * r], ev[3 * r + 1]);
+            (void)hipEventElapsedTime(&c, ev[3 * r + 1], ev[3 * r + 2]);
+            t1 += a;
+            t2 += c;
+        }
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    if (rc != VG_OK) return rc;
+    if (e != hipSuccess) return hip_fail(e, "timing synchronize");
+    *ms_tiles = t1 / reps;
+    *ms_reduce = t2 / reps;
+    return VG_OK;
+}
+
+}  // namespace
+
+extern "C" vg_status vg_batch_time_kernels(vg_batch* b, const double* poses, int32_t reps, float* ms) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    if (ms == nullptr) return invalid("ms is NULL");
+    if (reps < 1 || reps > 100000) return invalid("reps out of range");
+    VG_TRY(check_poses(poses, b->F));
+    VG_HIP(hipSetDevice(b->ctx->device));
+    hipStream_t st = b->ctx->stream;
+    std::memcpy(b->h_poses, poses, sizeof(double) * 12 * b->F);
+    VG_HIP(hipMemcpyAsync(b->d_poses, b->h_poses, sizeof(double) * 12 * b->F, hipMemcpyHostToDevice, st));
+    VG_TRY(time_device(b, reps, &ms[0], &ms[1]));
+    VG_TRY(linearize_host(b));   // warm-up (captures the graph if enabled)
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int r = 0; r < reps; ++r) VG_TRY(linearize_host(b));
+    const auto t1 = std::chrono::steady_clock::now();
+    ms[2] = (float)(std::chrono::duration<double, std::milli>(t1 - t0).count() / reps);
+    return VG_OK;
+}
+
+extern "C" vg_status vg_batch_tune(vg_batch* b, const double* poses, int32_t reps, int32_t* chosen) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    if (reps < 1 || reps > 1000) return invalid("reps out of range");
+    VG_TRY(check_poses(poses, b->F));
+    VG_HIP(hipSetDevice(b->ctx->device));
+    hipStream_t st = b->ctx->stream;
+    std::memcpy(b->h_poses, poses, sizeof(double) * 12 * b->F);
+    VG_HIP(hipMemcpyAsync(b->d_poses, b->h_poses, sizeof(double) * 12 * b->F, hipMemcpyHostToDevice, st));
+    const int blocks[] = {128, 256, 512};
+    const int tiles[] = {1024, 2048, 4096, 8192};
+    const int occ[] = {1, 2, 4};   // multiples of the full-occupancy workgroup count
+    float best = 1e30f;
+    int bb = b->block, bt = b->tile_points, bc = b->blocks_per_cu;
+    for (int tp : tiles) {
+        b->tile_points = tp;
+        build_tiles(b);
+        VG_TRY(upload_schedule(b));
+        for (int bl : blocks)
+            for (int oc : occ) {
+                b->block = bl;
+                b->blocks_per_cu = std::max(1, oc * 1024 / bl);
+                b->grid = (int)std::max<int64_t>(
+                    1, std::min<int64_t>((int64_t)b->ctx->num_cu * b->blocks_per_cu, (int64_t)b->h_tiles.size()));
+                float t1 = 0.f, t2 = 0.f;
+                VG_TRY(time_device(b, reps, &t1, &t2));
+                if (t1 + t2 < best) {
+                    best = t1 + t2;
+                    bb = bl;
+                    bt = tp;
+                    bc = b->blocks_per_cu;
+                }
+            }
+    }
+    b->block = bb;
+    b->tile_points = bt;
+    b->blocks_per_cu = bc;
+    build_tiles(b);
+    VG_TRY(upload_schedule(b));
+    if (chosen) {
+        chosen[0] = bb;
+        chosen[1] = bt;
+        chosen[2] = bc;
+    }
+    if (b->opt.tune_cache) {
+        std::ofstream outf(b->opt.tune_cache, std::ios::app);
+        if (outf) {
+            outf << "{\"key\": \"" << tune_key(b) << "\", \"block\": " << bb << ", \"tile_points\": " << bt
+                 << ", \"blocks_per_cu\": " << bc << ", \"ms\": " << best << "}\n";
+        }
+    }
+    return VG_OK;
+}

@@ -1,0 +1,95 @@
+// Device helpers shared by the VGICP kernels: key packing, hash probing and
+// small symmetric 3x3 algebra.
+#pragma once
+
+#include "vg_internal.h"
+
+namespace vg {
+
+// Relative voxel key (|k| < 8192 per axis) packed into 42 bits; x is the most
+// significant field, so ascending packed keys are ascending lexicographic keys.
+__host__ __device__ __forceinline__ bool key_in_range(int64_t k) {
+    return k >= -kKeyBias && k < kKeyBias;
+}
+
+__host__ __device__ __forceinline__ uint64_t pack_key(int64_t kx, int64_t ky, int64_t kz) {
+    return ((uint64_t)(kx + kKeyBias) << (2 * kKeyBits)) | ((uint64_t)(ky + kKeyBias) << kKeyBits) |
+           (uint64_t)(kz + kKeyBias);
+}
+
+__host__ __device__ __forceinline__ void unpack_key(uint64_t p, int64_t k[3]) {
+    const uint64_t m = (1ull << kKeyBits) - 1;
+    k[0] = (int64_t)((p >> (2 * kKeyBits)) & m) - kKeyBias;
+    k[1] = (int64_t)((p >> kKeyBits) & m) - kKeyBias;
+    k[2] = (int64_t)(p & m) - kKeyBias;
+}
+
+// Multiplicative (Fibonacci) hashing of the packed key to a slot.
+__host__ __device__ __forceinline__ uint32_t slot_of(uint64_t key, uint32_t log2cap) {
+    return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - log2cap));
+}
+
+// Open-addressing linear probe.  The table always holds an empty slot (load
+// factor <= 1/2), so the loop ends; the bound is a second guarantee.
+__device__ __forceinline__ int32_t probe(const uint64_t* __restrict__ slots, uint32_t log2cap, uint64_t key) {
+    const uint32_t mask = (1u << log2cap) - 1u;
+    uint32_t h = slot_of(key, log2cap);
+    for (uint32_t it = 0; it <= mask; ++it) {
+        const uint64_t s = slots[h];
+        if (s == kEmpty) return -1;
+        if ((s >> kIdxBits) == key) return (int32_t)(s & kIdxMask);
+        h = (h + 1u) & mask;
+    }
+    return -1;
+}
+
+// Inverse of a symmetric 3x3 matrix m = [a b c; b d e; c e f] via its adjugate.
+// Entries ordered xx, xy, xz, yy, yz, zz.
+template <typename T>
+__device__ __forceinline__ void sym3_inverse(const T m[6], T w[6]) {
+    const T a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5];
+    const T A = d * f - e * e;
+    const T B = c * e - b * f;
+    const T C = b * e - c * d;
+    const T D = a * f - c * c;
+    const T E = b * c - a * e;
+    const T Fv = a * d - b * b;
+    const T det = a * A + b * B + c * C;
+    const T s = T(1) / det;
+    w[0] = A * s;
+    w[1] = B * s;
+    w[2] = C * s;
+    w[3] = D * s;
+    w[4] = E * s;
+    w[5] = Fv * s;
+}
+
+// S = R C R^T for symmetric C (6 entries) and row-major R; S returned as 6 entries.
+template <typename T>
+__device__ __forceinline__ void rotate_cov(const T R[9], const T c[6], T S[6]) {
+    // RC = R * C (3x3)
+    T RC[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const T r0 = R[3 * i + 0], r1 = R[3 * i + 1], r2 = R[3 * i + 2];
+        RC[3 * i + 0] = r0 * c[0] + r1 * c[1] + r2 * c[2];
+        RC[3 * i + 1] = r0 * c[1] + r1 * c[3] + r2 * c[4];
+        RC[3 * i + 2] = r0 * c[2] + r1 * c[4] + r2 * c[5];
+    }
+    S[0] = RC[0] * R[0] + RC[1] * R[1] + RC[2] * R[2];
+    S[1] = RC[0] * R[3] + RC[1] * R[4] + RC[2] * R[5];
+    S[2] = RC[0] * R[6] + RC[1] * R[7] + RC[2] * R[8];
+    S[3] = RC[3] * R[3] + RC[4] * R[4] + RC[5] * R[5];
+    S[4] = RC[3] * R[6] + RC[4] * R[7] + RC[5] * R[8];
+    S[5] = RC[6] * R[6] + RC[7] * R[7] + RC[8] * R[8];
+}
+
+// y = W x for symmetric W (6 entries).
+template <typename T>
+__device__ __forceinline__ void sym3_mul(const T w[6], const T x[3], T y[3]) {
+    y[0] = w[0] * x[0] + w[1] * x[1] + w[2] * x[2];
+    y[1] = w[1] * x[0] + w[3] * x[1] + w[4] * x[2];
+    y[2] = w[2] * x[0] + w[4] * x[1] + w[5] * x[2];
+}
+
+}  // namespace vg

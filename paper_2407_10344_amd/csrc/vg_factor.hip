@@ -1,0 +1,759 @@
+// VGICP factor kernels for gfx950: transform + voxel-hash probe + fused-covariance
+// residual + per-point Gauss-Newton terms, reduced per work tile, then per factor.
+//
+// GLIM Sec. III-C: e = sum_l sum_k d^T W d, d = mu~ - (R mu + t),
+// W = (C~ + R C R^T)^-1 frozen at the linearization point, J = [R (mu)x, -R],
+// H = sum J^T W J, b = sum J^T W d.
+//
+// Work decomposition.  A batch is a flat list of tiles (factor, run of 64-point
+// chunks of its source).  A persistent grid pulls tiles from an atomic counter;
+// every tile writes one partial row (28 terms + inlier counts) in FP64 to its own
+// slot, and a second kernel sums each factor's rows in tile order, so results do
+// not depend on which workgroup ran which tile.
+//
+// Frames.  The terms are accumulated in the target orientation: with
+// z = R (mu - o_s) the per-point Jacobian is J = [(z)x, -I] Bd G where
+// Bd = diag(R, R) and G = [[I, 0], [-(o_s)x, I]] are the same for every point of a
+// factor, so the kernels sum H'' = sum [(z)x, -I]^T W [(z)x, -I] and
+// b'' = [u x z; -u] (u = W d) and the reduction applies H = G^T Bd^T H'' Bd G,
+// b = G^T Bd^T b'' once per factor in FP64.
+//
+// Precision modes.
+//  kC32: positions are stored as FP32 offsets from per-chunk FP64 anchors.  Per
+//        tile, each chunk's anchor is transformed in FP64 and split into an
+//        integer coarse-voxel key plus an FP32 remainder, so every per-point
+//        quantity (transformed position inside the coarse voxel, residual to a
+//        voxel mean stored relative to its voxel centre, lever arm) is small and
+//        FP32 keeps ~1e-7 m absolute accuracy anywhere in the map.  Lanes sum in
+//        FP32 with Kahan compensation, everything above a lane sums in FP64.
+//  kN32: absolute FP32 coordinates and FP32 sums everywhere.
+//  kF64: absolute FP64 coordinates and arithmetic.
+#include <type_traits>
+
+#include "vg_device.h"
+
+namespace vg {
+
+template <int PREC>
+struct PT {
+    using T = float;
+};
+template <>
+struct PT<kF64> {
+    using T = double;
+};
+
+// Upper-triangular index of (i, j), i <= j, of a 6x6 matrix.
+__host__ __device__ constexpr int tri(int i, int j) { return i * 6 - (i * (i - 1)) / 2 + (j - i); }
+
+template <typename T, bool KAHAN, int N>
+struct Acc {
+    T s[N];
+    T c[N];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            s[k] = T(0);
+            if constexpr (KAHAN) c[k] = T(0);
+        }
+    }
+    __device__ __forceinline__ void add(int k, T v) {
+        if constexpr (KAHAN) {
+            const T y = v - c[k];
+            const T t = s[k] + y;
+            c[k] = (t - s[k]) - y;
+            s[k] = t;
+        } else {
+            s[k] += v;
+        }
+    }
+    __device__ __forceinline__ T get(int k) const {
+        if constexpr (KAHAN) return s[k] - c[k];
+        else return s[k];
+    }
+    // the lane's sum with its compensation carried into FP64
+    __device__ __forceinline__ double get64(int k) const {
+        if constexpr (KAHAN) return (double)s[k] - (double)c[k];
+        else return (double)s[k];
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Gauss-Newton terms of one (point, voxel) pair in the target orientation.
+template <typename T, typename A>
+__device__ __forceinline__ void add_lin_terms(A& acc, const T d[3], const T w[6], const T z[3]) {
+    T u[3];
+    sym3_mul(w, d, u);
+    acc.add(0, d[0] * u[0] + d[1] * u[1] + d[2] * u[2]);
+    // P = (z)x W
+    const T P00 = -z[2] * w[1] + z[1] * w[2], P01 = -z[2] * w[3] + z[1] * w[4], P02 = -z[2] * w[4] + z[1] * w[5];
+    const T P10 = z[2] * w[0] - z[0] * w[2], P11 = z[2] * w[1] - z[0] * w[4], P12 = z[2] * w[2] - z[0] * w[5];
+    const T P20 = -z[1] * w[0] + z[0] * w[1], P21 = -z[1] * w[1] + z[0] * w[3], P22 = -z[1] * w[2] + z[0] * w[4];
+    // H''_ww = -P (z)x
+    acc.add(1 + tri(0, 0), -(P01 * z[2] - P02 * z[1]));
+    acc.add(1 + tri(0, 1), -(-P00 * z[2] + P02 * z[0]));
+    acc.add(1 + tri(0, 2), -(P00 * z[1] - P01 * z[0]));
+    acc.add(1 + tri(1, 1), -(-P10 * z[2] + P12 * z[0]));
+    acc.add(1 + tri(1, 2), -(P10 * z[1] - P11 * z[0]));
+    acc.add(1 + tri(2, 2), -(P20 * z[1] - P21 * z[0]));
+    // H''_wv = P
+    acc.add(1 + tri(0, 3), P00);
+    acc.add(1 + tri(0, 4), P01);
+    acc.add(1 + tri(0, 5), P02);
+    acc.add(1 + tri(1, 3), P10);
+    acc.add(1 + tri(1, 4), P11);
+    acc.add(1 + tri(1, 5), P12);
+    acc.add(1 + tri(2, 3), P20);
+    acc.add(1 + tri(2, 4), P21);
+    acc.add(1 + tri(2, 5), P22);
+    // H''_vv = W
+    acc.add(1 + tri(3, 3), w[0]);
+    acc.add(1 + tri(3, 4), w[1]);
+    acc.add(1 + tri(3, 5), w[2]);
+    acc.add(1 + tri(4, 4), w[3]);
+    acc.add(1 + tri(4, 5), w[4]);
+    acc.add(1 + tri(5, 5), w[5]);
+    // b'' = [u x z; -u]
+    acc.add(22, u[1] * z[2] - u[2] * z[1]);
+    acc.add(23, u[2] * z[0] - u[0] * z[2]);
+    acc.add(24, u[0] * z[1] - u[1] * z[0]);
+    acc.add(25, -u[0]);
+    acc.add(26, -u[1]);
+    acc.add(27, -u[2]);
+}
+
+struct TileShared {
+    double frac[kMaxTileChunks][3];  // anchor position inside its coarse voxel (kC32)
+    int32_t kb[kMaxTileChunks][3];   // coarse relative key of the anchor (kC32)
+    float za[kMaxTileChunks][3];     // R (anchor - o_s) (kC32)
+    float vc[kMaxTileChunks][3];     // anchor - T^-1 c (kC32, surface validation)
+};
+
+template <int MODE, int PREC, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_tiles(const FactorDesc* __restrict__ fac, const Tile* __restrict__ tiles,
+                                                 int32_t t_begin, int32_t t_end, const double* __restrict__ poses,
+                                                 double* __restrict__ partials, uint32_t* __restrict__ counter,
+                                                 int32_t validate, const double* __restrict__ grad_e,
+                                                 void* __restrict__ grad_points, int32_t points_dtype) {
+    using T = typename PT<PREC>::T;
+    constexpr int NW = BLOCK / 64;
+    constexpr bool KAHAN = (PREC == kC32);
+    constexpr int NT = (MODE == kLin) ? kTerms : (MODE == kEval ? 1 : 6);
+    __shared__ TileShared sh;
+    __shared__ double s_red[NW][kRow];
+    __shared__ int32_t s_tile;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = t_begin + (int32_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int32_t t = __builtin_amdgcn_readfirstlane(s_tile);
+        if (t >= t_end) break;
+        const Tile tile = tiles[t];
+        const FactorDesc* __restrict__ Fp = fac + tile.factor;
+        const int64_t n = Fp->n, n_pad = Fp->n_pad;
+        const int L = Fp->L;
+        const double* P = poses + 12 * tile.factor;
+        // pose in registers (uniform)
+        T R[9], tt[3];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) R[k] = (T)P[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) tt[k] = (T)P[9 + k];
+        // T^-1 c (source frame) for validation, in FP64
+        double cs[3] = {0, 0, 0};
+        if (validate) {
+            const double dc0 = Fp->viewpoint[0] - P[9], dc1 = Fp->viewpoint[1] - P[10], dc2 = Fp->viewpoint[2] - P[11];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) cs[i] = P[i] * dc0 + P[3 + i] * dc1 + P[6 + i] * dc2;
+        }
+        // ---------------------------------------------------------------- prologue: chunk anchors (kC32)
+        if constexpr (PREC == kC32) {
+            const LevelDesc& top = Fp->lv[L - 1];
+            for (int c = threadIdx.x; c < tile.nchunks; c += BLOCK) {
+                const double* a = Fp->anchor + 3 * (int64_t)(tile.chunk0 + c);
+                const double a0 = a[0], a1 = a[1], a2 = a[2];
+                const double o0 = a0 - Fp->src_origin[0], o1 = a1 - Fp->src_origin[1], o2 = a2 - Fp->src_origin[2];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const double ya = P[3 * i] * a0 + P[3 * i + 1] * a1 + P[3 * i + 2] * a2 + P[9 + i];
+                    const double kb = floor(ya * top.inv_r64);
+                    sh.frac[c][i] = ya - kb * top.r64;
+                    // clamped: anything this far is outside the packable key range anyway
+                    const double rel = fmin(fmax(kb - (double)top.K0[i], -1048576.0), 1048576.0);
+                    sh.kb[c][i] = (int32_t)rel;
+                    sh.za[c][i] = (float)(P[3 * i] * o0 + P[3 * i + 1] * o1 + P[3 * i + 2] * o2);
+                }
+                if (validate) {
+                    sh.vc[c][0] = (float)(a0 - cs[0]);
+                    sh.vc[c][1] = (float)(a1 - cs[1]);
+                    sh.vc[c][2] = (float)(a2 - cs[2]);
+                }
+            }
+            __syncthreads();
+        }
+        // ---------------------------------------------------------------- per-point work
+        Acc<T, KAHAN, NT> acc;
+        acc.zero();
+        int32_t inl[kMaxLevels] = {0, 0, 0, 0};
+        double ge = 0.0;
+        if constexpr (MODE == kBwd) ge = grad_e[tile.factor];
+
+        for (int c = wave; c < tile.nchunks; c += NW) {
+            const int64_t i = (int64_t)(tile.chunk0 + c) * kChunk + lane;
+            if (i >= n) continue;
+            // ---- load the point, transform it
+            // yl: transformed position (kC32: relative to the anchor's coarse voxel corner)
+            using TY = typename std::conditional<PREC == kC32, double, T>::type;
+            T x[3], cv[6], z[3];
+            TY yl[3];
+            bool vis = true;
+            if constexpr (PREC == kC32) {
+                // The residual d = mu~ - y cancels metre-scale positions down to
+                // centimetres, so the offset from the chunk anchor is rotated and
+                // placed relative to the voxel centre in FP64; d itself and every
+                // term downstream of it are FP32.
+                const float dx = Fp->dxyz[i], dy = Fp->dxyz[n_pad + i], dz = Fp->dxyz[2 * n_pad + i];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) cv[k] = Fp->cov[k * n_pad + i];
+                const double ddx = dx, ddy = dy, ddz = dz;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double rd = P[3 * a] * ddx + P[3 * a + 1] * ddy + P[3 * a + 2] * ddz;
+                    yl[a] = sh.frac[c][a] + rd;
+                    z[a] = sh.za[c][a] + (float)rd;
+                }
+                x[0] = dx;
+                x[1] = dy;
+                x[2] = dz;
+                if (validate) {
+                    const float s = (sh.vc[c][0] + dx) * Fp->nrm[i] + (sh.vc[c][1] + dy) * Fp->nrm[n_pad + i] +
+                                    (sh.vc[c][2] + dz) * Fp->nrm[2 * n_pad + i];
+                    vis = !(s > 0.0f);
+                }
+            } else if constexpr (PREC == kN32) {
+                x[0] = Fp->axyz[i];
+                x[1] = Fp->axyz[n_pad + i];
+                x[2] = Fp->axyz[2 * n_pad + i];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) cv[k] = Fp->cov[k * n_pad + i];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    z[a] = R[3 * a] * x[0] + R[3 * a + 1] * x[1] + R[3 * a + 2] * x[2];
+                    yl[a] = z[a] + tt[a];
+                }
+                if (validate) {
+                    const float s = (x[0] - (float)cs[0]) * Fp->nrm[i] + (x[1] - (float)cs[1]) * Fp->nrm[n_pad + i] +
+                                    (x[2] - (float)cs[2]) * Fp->nrm[2 * n_pad + i];
+                    vis = !(s > 0.0f);
+                }
+            } else {
+                x[0] = Fp->xyz64[i];
+                x[1] = Fp->xyz64[n_pad + i];
+                x[2] = Fp->xyz64[2 * n_pad + i];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) cv[k] = Fp->cov64[k * n_pad + i];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    z[a] = R[3 * a] * x[0] + R[3 * a + 1] * x[1] + R[3 * a + 2] * x[2];
+                    yl[a] = z[a] + tt[a];
+                }
+                if (validate) {
+                    const double s = (x[0] - cs[0]) * Fp->nrm64[i] + (x[1] - cs[1]) * Fp->nrm64[n_pad + i] +
+                                     (x[2] - cs[2]) * Fp->nrm64[2 * n_pad + i];
+                    vis = !(s > 0.0);
+                }
+            }
+            if (!vis) {
+                if constexpr (MODE == kBwd) {
+                    if (grad_points != nullptr && Fp->grad_exclusive) {
+                        const int64_t row = Fp->grad_offset + Fp->perm[i];
+                        if (points_dtype == 0) {
+                            float* g = (float*)grad_points + 3 * row;
+                            g[0] = 0.f; g[1] = 0.f; g[2] = 0.f;
+                        } else {
+                            double* g = (double*)grad_points + 3 * row;
+                            g[0] = 0.0; g[1] = 0.0; g[2] = 0.0;
+                        }
+                    }
+                }
+                continue;
+            }
+            // ---- per level: key, probe, terms
+            // S = R C R^T, once per point (FP64 in the compensated mode, where the
+            // fused covariance and its inverse are formed in FP64: both covariances
+            // are near-singular, so FP32 rounding of either one would move W by
+            // ~1e-4 relative along the surface normal)
+            using TS = typename std::conditional<PREC == kC32, double, T>::type;
+            TS S[6];
+            bool haveS = false;
+            T gp[3] = {T(0), T(0), T(0)};
+#pragma unroll
+            for (int l = 0; l < kMaxLevels; ++l) {
+                if (l >= L) break;
+                const LevelDesc& lv = Fp->lv[l];
+                int64_t kq[3];
+                TY pc[3];   // position relative to the voxel centre (kC32), absolute otherwise
+                if constexpr (PREC == kC32) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const double j = floor(yl[a] * lv.inv_r64);
+                        kq[a] = (int64_t)sh.kb[c][a] * lv.scale + (int64_t)j;
+                        pc[a] = yl[a] - (j + 0.5) * lv.r64;
+                    }
+                } else if constexpr (PREC == kN32) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const float q = floorf(yl[a] * lv.inv_r);
+                        kq[a] = (int64_t)q - lv.K0[a];
+                        pc[a] = yl[a];
+                    }
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const double q = floor(yl[a] * lv.inv_r64);
+                        kq[a] = (int64_t)q - lv.K0[a];
+                        pc[a] = yl[a];
+                    }
+                }
+                if (!(key_in_range(kq[0]) && key_in_range(kq[1]) && key_in_range(kq[2]))) continue;
+                const int32_t v = probe(lv.slots, lv.log2cap, pack_key(kq[0], kq[1], kq[2]));
+                if (v < 0) continue;
+                inl[l] += 1;
+                if (!haveS) {
+                    if constexpr (PREC == kC32) {
+                        double R64[9], C64[6];
+#pragma unroll
+                        for (int k = 0; k < 9; ++k) R64[k] = P[k];
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) C64[k] = (double)cv[k];
+                        rotate_cov(R64, C64, S);
+                    } else {
+                        rotate_cov(R, cv, S);
+                    }
+                    haveS = true;
+                }
+                T mv[3];
+                T W[6];
+                if constexpr (PREC == kC32) {
+                    const float4* r4 = reinterpret_cast<const float4*>(lv.rec32 + (int64_t)v * kRec32);
+                    const float4 q0 = r4[0], q1 = r4[1], q2 = r4[2], q3 = r4[3];
+                    mv[0] = q0.x; mv[1] = q0.y; mv[2] = q0.z;
+                    double M[6], W64[6];
+                    M[0] = ((double)q0.w + (double)q2.y) + S[0];
+                    M[1] = ((double)q1.x + (double)q2.z) + S[1];
+                    M[2] = ((double)q1.y + (double)q2.w) + S[2];
+                    M[3] = ((double)q1.z + (double)q3.x) + S[3];
+                    M[4] = ((double)q1.w + (double)q3.y) + S[4];
+                    M[5] = ((double)q2.x + (double)q3.z) + S[5];
+                    sym3_inverse(M, W64);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) W[k] = (float)W64[k];
+                } else {
+                    T cvv[6];
+                    if constexpr (PREC == kN32) {
+                        const float4* r4 = reinterpret_cast<const float4*>(lv.recN + (int64_t)v * kRecN);
+                        const float4 q0 = r4[0], q1 = r4[1], q2 = r4[2];
+                        mv[0] = q0.x; mv[1] = q0.y; mv[2] = q0.z;
+                        cvv[0] = q0.w; cvv[1] = q1.x; cvv[2] = q1.y; cvv[3] = q1.z; cvv[4] = q1.w; cvv[5] = q2.x;
+                    } else {
+                        const double2* r2 = reinterpret_cast<const double2*>(lv.rec64 + (int64_t)v * kRec64);
+                        const double2 q0 = r2[0], q1 = r2[1], q2 = r2[2], q3 = r2[3], q4 = r2[4];
+                        mv[0] = q0.x; mv[1] = q0.y; mv[2] = q1.x;
+                        cvv[0] = q1.y; cvv[1] = q2.x; cvv[2] = q2.y; cvv[3] = q3.x; cvv[4] = q3.y; cvv[5] = q4.x;
+                    }
+                    T M[6];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) M[k] = cvv[k] + S[k];
+                    sym3_inverse(M, W);
+                }
+                T d[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) d[a] = (T)((TY)mv[a] - pc[a]);
+                if constexpr (MODE == kLin) {
+                    add_lin_terms(acc, d, W, z);
+                } else if constexpr (MODE == kEval) {
+                    T u[3];
+                    sym3_mul(W, d, u);
+                    acc.add(0, d[0] * u[0] + d[1] * u[1] + d[2] * u[2]);
+                } else {
+                    T u[3], Su[3], Sf[6];
+                    sym3_mul(W, d, u);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) Sf[k] = (T)S[k];
+                    sym3_mul(Sf, u, Su);
+                    const T q0 = z[0] + Su[0], q1 = z[1] + Su[1], q2 = z[2] + Su[2];
+                    acc.add(0, T(2) * (u[1] * q2 - u[2] * q1));
+                    acc.add(1, T(2) * (u[2] * q0 - u[0] * q2));
+                    acc.add(2, T(2) * (u[0] * q1 - u[1] * q0));
+                    acc.add(3, T(-2) * u[0]);
+                    acc.add(4, T(-2) * u[1]);
+                    acc.add(5, T(-2) * u[2]);
+                    // de/dmu = -2 R^T u (source frame)
+                    gp[0] += T(-2) * (R[0] * u[0] + R[3] * u[1] + R[6] * u[2]);
+                    gp[1] += T(-2) * (R[1] * u[0] + R[4] * u[1] + R[7] * u[2]);
+                    gp[2] += T(-2) * (R[2] * u[0] + R[5] * u[1] + R[8] * u[2]);
+                }
+            }
+            if constexpr (MODE == kBwd) {
+                if (grad_points != nullptr) {
+                    const int64_t row = Fp->grad_offset + Fp->perm[i];
+                    if (points_dtype == 0) {
+                        float* g = (float*)grad_points + 3 * row;
+                        const float g0 = (float)(ge * (double)gp[0]), g1 = (float)(ge * (double)gp[1]),
+                                    g2 = (float)(ge * (double)gp[2]);
+                        if (Fp->grad_exclusive) {
+                            g[0] = g0; g[1] = g1; g[2] = g2;
+                        } else {
+                            atomicAdd(g + 0, g0);
+                            atomicAdd(g + 1, g1);
+                            atomicAdd(g + 2, g2);
+                        }
+                    } else {
+                        double* g = (double*)grad_points + 3 * row;
+                        const double g0 = ge * (double)gp[0], g1 = ge * (double)gp[1], g2 = ge * (double)gp[2];
+                        if (Fp->grad_exclusive) {
+                            g[0] = g0; g[1] = g1; g[2] = g2;
+                        } else {
+                            atomicAdd(g + 0, g0);
+                            atomicAdd(g + 1, g1);
+                            atomicAdd(g + 2, g2);
+                        }
+                    }
+                }
+            }
+        }
+        // ---------------------------------------------------------------- reduction of the tile
+        // lanes -> wave -> tile: FP64 except kN32, which stays FP32 end to end
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            if constexpr (PREC == kN32) {
+                const float v = wave_sum(acc.get(k));
+                if (lane == 0) s_red[wave][k] = (double)v;
+            } else {
+                const double v = wave_sum(acc.get64(k));
+                if (lane == 0) s_red[wave][k] = v;
+            }
+        }
+        if constexpr (MODE != kBwd) {
+#pragma unroll
+            for (int l = 0; l < kMaxLevels; ++l) {
+                const int32_t v = wave_sum(inl[l]);
+                if (lane == 0) s_red[wave][kTerms + l] = (double)v;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < kRow) {
+            const int k = threadIdx.x;
+            double s = 0.0;
+            if constexpr (PREC == kN32) {
+                if (k < kTerms) {
+                    float sf = 0.f;
+                    for (int w = 0; w < NW; ++w) sf += (float)s_red[w][k];
+                    s = (double)sf;
+                } else {
+                    for (int w = 0; w < NW; ++w) s += s_red[w][k];
+                }
+            } else {
+                for (int w = 0; w < NW; ++w) s += s_red[w][k];
+            }
+            const bool used = (k < NT) || (MODE != kBwd && k >= kTerms);
+            partials[(int64_t)t * kRow + k] = used ? s : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+// Per-factor reduction of tile rows in tile order (FP64; FP32 for kN32) and the
+// frame change H = G^T Bd^T H'' Bd G, b = G^T Bd^T b''.  One 64-thread block per
+// factor.  Block 0 also re-arms the tile counter for the next launch.
+template <int MODE, int PREC>
+__global__ __launch_bounds__(64) void k_reduce(const FactorDesc* __restrict__ fac, const int32_t* __restrict__ tile_first,
+                                               int32_t f0, const double* __restrict__ partials,
+                                               const double* __restrict__ poses, double* __restrict__ out,
+                                               int64_t* __restrict__ inliers, uint32_t* __restrict__ counter,
+                                               const double* __restrict__ grad_e, const double* __restrict__ jr,
+                                               double* __restrict__ grad_xi) {
+    __shared__ double s[kRow];
+    const int f = f0 + blockIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
+    const int k = threadIdx.x;
+    if (k < kRow) {
+        const int32_t a = tile_first[f], bnd = tile_first[f + 1];
+        if constexpr (PREC == kN32) {
+            float sf = 0.f;
+            double si = 0.0;
+            for (int32_t t = a; t < bnd; ++t) {
+                const double v = partials[(int64_t)t * kRow + k];
+                sf += (float)v;
+                si += v;
+            }
+            s[k] = (k >= kTerms) ? si : (double)sf;
+        } else {
+            double acc = 0.0;
+            for (int32_t t = a; t < bnd; ++t) acc += partials[(int64_t)t * kRow + k];
+            s[k] = acc;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const FactorDesc& F = fac[f];
+    const double* P = poses + 12 * f;
+    const double* R = P;
+    const double o[3] = {PREC == kC32 ? F.src_origin[0] : 0.0, PREC == kC32 ? F.src_origin[1] : 0.0,
+                         PREC == kC32 ? F.src_origin[2] : 0.0};
+    if constexpr (MODE == kEval) {
+        out[f] = s[0];
+        return;
+    }
+    if constexpr (MODE == kBwd) {
+        // g' = Bd^T g'' (rotate both halves back to the source frame), g = G^T g'
+        double gw[3], gv[3], g[6];
+        for (int i = 0; i < 3; ++i) {
+            gw[i] = R[i] * s[0] + R[3 + i] * s[1] + R[6 + i] * s[2];
+            gv[i] = R[i] * s[3] + R[3 + i] * s[4] + R[6 + i] * s[5];
+        }
+        g[0] = gw[0] + (o[1] * gv[2] - o[2] * gv[1]);
+        g[1] = gw[1] + (o[2] * gv[0] - o[0] * gv[2]);
+        g[2] = gw[2] + (o[0] * gv[1] - o[1] * gv[0]);
+        g[3] = gv[0];
+        g[4] = gv[1];
+        g[5] = gv[2];
+        const double ge = grad_e[f];
+        for (int i = 0; i < 6; ++i) {
+            double v = g[i];
+            if (jr != nullptr) {
+                v = 0.0;
+                for (int j = 0; j < 6; ++j) v += jr[36 * (int64_t)f + 6 * j + i] * g[j];
+            }
+            grad_xi[6 * (int64_t)f + i] = ge * v;
+        }
+        return;
+    }
+    // unpack H'' (symmetric) and b''
+    double Hs[36];
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) {
+            Hs[6 * i + j] = s[1 + tri(i, j)];
+            Hs[6 * j + i] = s[1 + tri(i, j)];
+        }
+    // M = Bd G (6x6): [[R, 0], [-R (o)x, R]]
+    double M[36] = {0};
+    double Ox[9] = {0, -o[2], o[1], o[2], 0, -o[0], -o[1], o[0], 0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            M[6 * i + j] = R[3 * i + j];
+            M[6 * (3 + i) + 3 + j] = R[3 * i + j];
+            double ro = 0.0;
+            for (int q = 0; q < 3; ++q) ro += R[3 * i + q] * Ox[3 * q + j];
+            M[6 * (3 + i) + j] = -ro;
+        }
+    double HM[36];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double acc = 0.0;
+            for (int q = 0; q < 6; ++q) acc += Hs[6 * i + q] * M[6 * q + j];
+            HM[6 * i + j] = acc;
+        }
+    double* o_row = out + (int64_t)kOutRow * f;
+    o_row[0] = s[0];
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) {
+            double acc = 0.0;
+            for (int q = 0; q < 6; ++q) acc += M[6 * q + i] * HM[6 * q + j];
+            o_row[1 + 6 * i + j] = acc;
+            o_row[1 + 6 * j + i] = acc;
+        }
+    for (int i = 0; i < 6; ++i) {
+        double acc = 0.0;
+        for (int q = 0; q < 6; ++q) acc += M[6 * q + i] * s[22 + q];
+        o_row[37 + i] = acc;
+    }
+    if (inliers != nullptr)
+        for (int l = 0; l < F.L; ++l) inliers[(int64_t)F.L * f + l] = (int64_t)s[kTerms + l];
+}
+
+// Correspondences of one factor (keys and found flags in caller order).
+template <int PREC>
+__global__ void k_correspondences(const FactorDesc* __restrict__ fac, int64_t factor, const double* __restrict__ pose,
+                                  int32_t validate, int64_t* __restrict__ keys, int32_t* __restrict__ found) {
+    using T = typename PT<PREC>::T;
+    const FactorDesc& F = fac[factor];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= F.n) return;
+    const double* P = pose;
+    const int L = F.L;
+    const int64_t row = F.perm[i];
+    double cs[3] = {0, 0, 0};
+    if (validate) {
+        const double dc0 = F.viewpoint[0] - P[9], dc1 = F.viewpoint[1] - P[10], dc2 = F.viewpoint[2] - P[11];
+        for (int a = 0; a < 3; ++a) cs[a] = P[a] * dc0 + P[3 + a] * dc1 + P[6 + a] * dc2;
+    }
+    using TY = typename std::conditional<PREC == kC32, double, T>::type;
+    T R[9], tt[3];
+    TY yl[3];
+    for (int k = 0; k < 9; ++k) R[k] = (T)P[k];
+    for (int k = 0; k < 3; ++k) tt[k] = (T)P[9 + k];
+    bool vis = true;
+    int32_t kb[3] = {0, 0, 0};
+    const int64_t n_pad = F.n_pad;
+    if constexpr (PREC == kC32) {
+        const LevelDesc& top = F.lv[L - 1];
+        const int64_t c = i / kChunk;
+        const double* a = F.anchor + 3 * c;
+        const float dx = F.dxyz[i], dy = F.dxyz[n_pad + i], dz = F.dxyz[2 * n_pad + i];
+        for (int q = 0; q < 3; ++q) {
+            const double ya = P[3 * q] * a[0] + P[3 * q + 1] * a[1] + P[3 * q + 2] * a[2] + P[9 + q];
+            const double kbd = floor(ya * top.inv_r64);
+            const double frac = ya - kbd * top.r64;
+            kb[q] = (int32_t)fmin(fmax(kbd - (double)top.K0[q], -1048576.0), 1048576.0);
+            yl[q] = frac + (P[3 * q] * (double)dx + P[3 * q + 1] * (double)dy + P[3 * q + 2] * (double)dz);
+        }
+        if (validate) {
+            const float s = ((float)(a[0] - cs[0]) + dx) * F.nrm[i] + ((float)(a[1] - cs[1]) + dy) * F.nrm[n_pad + i] +
+                            ((float)(a[2] - cs[2]) + dz) * F.nrm[2 * n_pad + i];
+            vis = !(s > 0.0f);
+        }
+    } else if constexpr (PREC == kN32) {
+        const float x0 = F.axyz[i], x1 = F.axyz[n_pad + i], x2 = F.axyz[2 * n_pad + i];
+        for (int q = 0; q < 3; ++q) yl[q] = (R[3 * q] * x0 + R[3 * q + 1] * x1 + R[3 * q + 2] * x2) + tt[q];
+        if (validate) {
+            const float s = (x0 - (float)cs[0]) * F.nrm[i] + (x1 - (float)cs[1]) * F.nrm[n_pad + i] +
+                            (x2 - (float)cs[2]) * F.nrm[2 * n_pad + i];
+            vis = !(s > 0.0f);
+        }
+    } else {
+        const double x0 = F.xyz64[i], x1 = F.xyz64[n_pad + i], x2 = F.xyz64[2 * n_pad + i];
+        for (int q = 0; q < 3; ++q) yl[q] = (R[3 * q] * x0 + R[3 * q + 1] * x1 + R[3 * q + 2] * x2) + tt[q];
+        if (validate) {
+            const double s = (x0 - cs[0]) * F.nrm64[i] + (x1 - cs[1]) * F.nrm64[n_pad + i] +
+                             (x2 - cs[2]) * F.nrm64[2 * n_pad + i];
+            vis = !(s > 0.0);
+        }
+    }
+    for (int l = 0; l < L; ++l) {
+        const LevelDesc& lv = F.lv[l];
+        int64_t kq[3];
+        for (int q = 0; q < 3; ++q) {
+            if constexpr (PREC == kC32) {
+                kq[q] = (int64_t)kb[q] * lv.scale + (int64_t)floor(yl[q] * lv.inv_r64);
+            } else if constexpr (PREC == kN32) {
+                kq[q] = (int64_t)floorf(yl[q] * lv.inv_r) - lv.K0[q];
+            } else {
+                kq[q] = (int64_t)floor(yl[q] * lv.inv_r64) - lv.K0[q];
+            }
+            keys[(row * L + l) * 3 + q] = kq[q] + lv.K0[q];
+        }
+        int32_t fnd;
+        if (!vis) fnd = -1;
+        else if (!(key_in_range(kq[0]) && key_in_range(kq[1]) && key_in_range(kq[2]))) fnd = 0;
+        else fnd = probe(lv.slots, lv.log2cap, pack_key(kq[0], kq[1], kq[2])) >= 0 ? 1 : 0;
+        found[row * L + l] = fnd;
+    }
+}
+
+__global__ void k_fill_zero(uint32_t* p, int64_t n_words) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_words) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------- host launchers
+
+template <int MODE, int PREC>
+static vg_status launch_tiles_t(vg_batch* b, const double* d_poses, int32_t t0, int32_t t1, int grid,
+                                const double* d_grad_e, void* d_grad_points, int points_dtype) {
+    hipStream_t st = b->ctx->stream;
+    const int v = b->opt.surface_validation;
+    switch (b->block) {
+        case 64:
+            k_tiles<MODE, PREC, 64><<<grid, 64, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, b->d_partials,
+                                                        b->d_counter, v, d_grad_e, d_grad_points, points_dtype);
+            break;
+        case 128:
+            k_tiles<MODE, PREC, 128><<<grid, 128, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, b->d_partials,
+                                                          b->d_counter, v, d_grad_e, d_grad_points, points_dtype);
+            break;
+        case 512:
+            k_tiles<MODE, PREC, 512><<<grid, 512, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, b->d_partials,
+                                                          b->d_counter, v, d_grad_e, d_grad_points, points_dtype);
+            break;
+        default:
+            k_tiles<MODE, PREC, 256><<<grid, 256, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, b->d_partials,
+                                                          b->d_counter, v, d_grad_e, d_grad_points, points_dtype);
+            break;
+    }
+    VG_HIP(hipGetLastError());
+    return VG_OK;
+}
+
+vg_status launch_tiles(vg_batch* b, int mode, const double* d_poses, int32_t t0, int32_t t1, int grid,
+                       const double* d_grad_e, void* d_grad_points, int points_dtype) {
+    if (grid < 1) grid = 1;
+    const int p = b->opt.precision;
+#define VG_DISPATCH(M)                                                                                      \
+    if (p == kC32) return launch_tiles_t<M, kC32>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype); \
+    if (p == kN32) return launch_tiles_t<M, kN32>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype); \
+    return launch_tiles_t<M, kF64>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype);
+    if (mode == kLin) { VG_DISPATCH(kLin) }
+    if (mode == kEval) { VG_DISPATCH(kEval) }
+    VG_DISPATCH(kBwd)
+#undef VG_DISPATCH
+}
+
+template <int MODE, int PREC>
+static void reduce_t(vg_batch* b, const double* d_poses, int32_t f0, int32_t f1, double* d_out, int64_t* d_inl,
+                     const double* d_grad_e, const double* d_jr, double* d_grad_xi) {
+    k_reduce<MODE, PREC><<<f1 - f0, 64, 0, b->ctx->stream>>>(b->d_fac, b->d_tile_first, f0, b->d_partials, d_poses,
+                                                             d_out, d_inl, b->d_counter, d_grad_e, d_jr, d_grad_xi);
+}
+
+vg_status launch_reduce(vg_batch* b, int mode, const double* d_poses, int32_t f0, int32_t f1, double* d_out,
+                        int64_t* d_inliers, const double* d_grad_e, const double* d_jr, double* d_grad_xi) {
+    if (f1 <= f0) return VG_OK;
+    const int p = b->opt.precision;
+#define VG_R(M)                                                                               \
+    if (p == kC32) reduce_t<M, kC32>(b, d_poses, f0, f1, d_out, d_inliers, d_grad_e, d_jr, d_grad_xi); \
+    else if (p == kN32) reduce_t<M, kN32>(b, d_poses, f0, f1, d_out, d_inliers, d_grad_e, d_jr, d_grad_xi); \
+    else reduce_t<M, kF64>(b, d_poses, f0, f1, d_out, d_inliers, d_grad_e, d_jr, d_grad_xi);
+    if (mode == kLin) { VG_R(kLin) }
+    else if (mode == kEval) { VG_R(kEval) }
+    else { VG_R(kBwd) }
+#undef VG_R
+    VG_HIP(hipGetLastError());
+    return VG_OK;
+}
+
+vg_status launch_correspondences(vg_batch* b, const double* d_pose, int64_t factor, int64_t* d_keys,
+                                 int32_t* d_found) {
+    const int64_t n = b->h_fac[factor].n;
+    if (n == 0) return VG_OK;
+    const int grid = (int)((n + 255) / 256);
+    const int v = b->opt.surface_validation;
+    hipStream_t st = b->ctx->stream;
+    if (b->opt.precision == kC32)
+        k_correspondences<kC32><<<grid, 256, 0, st>>>(b->d_fac, factor, d_pose, v, d_keys, d_found);
+    else if (b->opt.precision == kN32)
+        k_correspondences<kN32><<<grid, 256, 0, st>>>(b->d_fac, factor, d_pose, v, d_keys, d_found);
+    else
+        k_correspondences<kF64><<<grid, 256, 0, st>>>(b->d_fac, factor, d_pose, v, d_keys, d_found);
+    VG_HIP(hipGetLastError());
+    return VG_OK;
+}
+
+vg_status launch_zero(vg_context* ctx, void* d_ptr, size_t bytes) {
+    if (bytes == 0) return VG_OK;
+    const int64_t words = (int64_t)((bytes + 3) / 4);
+    const int grid = (int)((words + 255) / 256);
+    k_fill_zero<<<grid, 256, 0, ctx->stream>>>((uint32_t*)d_ptr, words);
+    VG_HIP(hipGetLastError());
+    return VG_OK;
+}
+
+}  // namespace vg

@@ -1,0 +1,209 @@
+// Internal declarations of the VGICP device library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "vgicp.h"
+
+namespace vg {
+
+// ---------------------------------------------------------------- constants
+
+constexpr int kMaxLevels = 4;
+constexpr int kChunk = 64;              // points per anchor chunk == one wavefront
+constexpr int kKeyBits = 14;            // bits per axis of a packed relative voxel key
+constexpr int kKeyBias = 1 << (kKeyBits - 1);   // relative keys live in [-8192, 8191]
+constexpr int kIdxBits = 22;            // voxel index bits of a hash slot
+constexpr uint64_t kIdxMask = (1ull << kIdxBits) - 1;
+constexpr int64_t kMaxVoxels = (int64_t)kIdxMask - 1;   // idx 0x3FFFFF never valid
+constexpr uint64_t kEmpty = ~0ull;      // empty hash slot (never a valid key|idx)
+constexpr int kRow = 32;                // partial row: 28 terms + 4 inlier counts
+constexpr int kTerms = 28;              // e, 21 upper-triangular H, 6 b
+constexpr int kMaxTileChunks = 128;     // at most 8192 points per tile
+constexpr int kRec32 = 16;              // floats per compensated voxel record (64 B)
+constexpr int kRecN = 12;               // floats per absolute-FP32 voxel record
+constexpr int kRec64 = 10;              // doubles per FP64 voxel record
+constexpr int kOutRow = 43;             // e, H (36), b (6)
+
+enum Mode { kLin = 0, kEval = 1, kBwd = 2 };
+enum Prec { kN32 = VG_FP32, kC32 = VG_FP32_COMPENSATED, kF64 = VG_FP64 };
+
+// ---------------------------------------------------------------- device descriptors
+
+// One level of a target voxel map as the kernels see it.
+struct LevelDesc {
+    const uint64_t* slots;   // 2^log2cap slots: (packed relative key << 22) | voxel index
+    const float* rec32;      // V x 16: mean - voxel centre (3), cov hi (6), cov lo (6), count
+    const float* recN;       // V x 12: FP32 absolute mean (3), cov (6), pad
+    const double* rec64;     // V x 10: absolute mean (3), cov (6), pad
+    uint32_t log2cap;
+    int32_t scale;           // r_coarsest / r_l (power of two)
+    float r, inv_r;
+    double r64, inv_r64;
+    int64_t K0[3];           // absolute key of the map origin at this level
+};
+
+// One factor: a source cloud (internal Morton order) matched into a target map.
+struct FactorDesc {
+    const float* dxyz;       // 3 x n_pad SoA offsets from the chunk anchor
+    const float* cov;        // 6 x n_pad SoA covariances
+    const float* nrm;        // 3 x n_pad SoA normals or nullptr
+    const double* anchor;    // n_chunks x 3 absolute anchors (source frame)
+    const float* axyz;       // 3 x n_pad absolute FP32 positions
+    const double* xyz64;     // 3 x n_pad absolute FP64 positions
+    const double* cov64;     // 6 x n_pad FP64 covariances
+    const double* nrm64;     // 3 x n_pad FP64 normals or nullptr
+    const int32_t* perm;     // internal index -> caller index
+    int64_t n, n_pad;
+    int64_t grad_offset;     // first row of this source in the concatenated point gradient
+    int32_t grad_exclusive;  // 1 if no other factor of the batch uses this source
+    int32_t L;
+    double src_origin[3];    // o_s: the re-centring origin of the source
+    double viewpoint[3];     // target viewpoint (target frame) for surface validation
+    LevelDesc lv[kMaxLevels];
+};
+
+struct Tile {
+    int32_t factor;
+    int32_t chunk0;          // first chunk of the factor's source
+    int32_t nchunks;
+    int32_t pad;
+};
+
+// ---------------------------------------------------------------- host objects
+
+struct Level {
+    double r = 0;
+    int64_t K0[3] = {0, 0, 0};
+    int64_t V = 0;
+    uint32_t log2cap = 0;
+    uint64_t* slots = nullptr;
+    float* rec32 = nullptr;
+    float* recN = nullptr;
+    double* rec64 = nullptr;
+    uint64_t* keys = nullptr;   // V packed relative keys, ascending
+    int32_t* counts = nullptr;  // V
+};
+
+}  // namespace vg
+
+struct vg_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int num_cu = 0;
+    std::string arch;
+    std::string name;
+    uint32_t magic = 0;
+};
+
+struct vg_voxelmap {
+    vg_context* ctx = nullptr;
+    int L = 0;
+    double origin[3] = {0, 0, 0};
+    vg::Level lv[vg::kMaxLevels];
+    int users = 0;
+    uint32_t magic = 0;
+};
+
+struct vg_source {
+    vg_context* ctx = nullptr;
+    int64_t n = 0, n_pad = 0, n_chunks = 0;
+    double origin[3] = {0, 0, 0};
+    bool has_normals = false;
+    float* dxyz = nullptr;
+    float* cov = nullptr;
+    float* nrm = nullptr;
+    double* anchor = nullptr;
+    float* axyz = nullptr;
+    double* xyz64 = nullptr;
+    double* cov64 = nullptr;
+    double* nrm64 = nullptr;
+    int32_t* perm = nullptr;   // internal -> caller
+    int users = 0;
+    uint32_t magic = 0;
+};
+
+struct vg_batch {
+    vg_context* ctx = nullptr;
+    int64_t F = 0;
+    int L = 0;
+    vg_batch_options opt{};
+    std::vector<vg_source*> src;
+    std::vector<vg_voxelmap*> tgt;
+    std::vector<vg::FactorDesc> h_fac;
+    std::vector<vg::Tile> h_tiles;
+    std::vector<int32_t> h_tile_first;   // F + 1
+    std::vector<int64_t> grad_offsets;   // per unique source
+    int64_t total_points = 0;
+    int64_t grad_rows = 0;               // rows of the concatenated point gradient
+    int block = 256, tile_points = 2048, grid = 0, blocks_per_cu = 0;
+    // device buffers
+    vg::FactorDesc* d_fac = nullptr;
+    vg::Tile* d_tiles = nullptr;
+    int32_t* d_tile_first = nullptr;
+    double* d_partials = nullptr;
+    uint32_t* d_counter = nullptr;
+    double* d_poses = nullptr;
+    double* d_out = nullptr;        // F x 43
+    int64_t* d_inliers = nullptr;   // F x L
+    double* d_e = nullptr;          // F (evaluate)
+    double* d_lm = nullptr;         // LM scratch
+    // pinned host staging (one upload, one download)
+    double* h_poses = nullptr;
+    double* h_out = nullptr;
+    int64_t* h_inliers = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint32_t magic = 0;
+};
+
+namespace vg {
+
+// ---------------------------------------------------------------- error state
+
+void set_error(const std::string& msg);
+vg_status hip_fail(hipError_t e, const char* what);
+
+#define VG_HIP(call)                                        \
+    do {                                                    \
+        hipError_t _e = (call);                             \
+        if (_e != hipSuccess) return vg::hip_fail(_e, #call);\
+    } while (0)
+
+// ---------------------------------------------------------------- launchers (device code)
+
+vg_status build_level(vg_context* ctx, const double* d_xyz, const double* d_cov, int64_t n, double r,
+                      const double origin[3], Level* out, uint64_t* d_scratch_keys, int32_t* d_scratch_idx,
+                      void* d_sort_tmp, size_t sort_tmp_bytes, int32_t* d_flag);
+size_t build_level_scratch_bytes(int64_t n);
+vg_status export_level(vg_context* ctx, const Level& lv, int64_t* keys, double* means, double* covs,
+                       int64_t* counts);
+void free_level(Level* lv);
+
+vg_status layout_source(vg_context* ctx, vg_source* s, const double* d_xyz, const double* d_cov,
+                        const double* d_nrm);
+vg_status set_source_points(vg_context* ctx, vg_source* s, const void* d_xyz, int dtype);
+
+// launch the tile kernel over tiles [t0, t1) and the reduction over factors [f0, f1)
+vg_status launch_tiles(vg_batch* b, int mode, const double* d_poses, int32_t t0, int32_t t1, int grid,
+                       const double* d_grad_e, void* d_grad_points, int points_dtype);
+vg_status launch_reduce(vg_batch* b, int mode, const double* d_poses, int32_t f0, int32_t f1, double* d_out,
+                        int64_t* d_inliers, const double* d_grad_e, const double* d_jr, double* d_grad_xi);
+vg_status launch_correspondences(vg_batch* b, const double* d_pose, int64_t factor, int64_t* d_keys,
+                                 int32_t* d_found);
+vg_status launch_zero(vg_context* ctx, void* d_ptr, size_t bytes);
+vg_status launch_se3_retract(vg_context* ctx, int64_t F, const double* d_T0, const double* d_xi, double* d_T,
+                             double* d_jr);
+vg_status launch_lm_propose(vg_batch* b, const double* d_out, double* d_state, double* d_poses,
+                            double* d_cand);
+vg_status launch_lm_init(vg_batch* b, double* d_state, double lambda0);
+vg_status launch_lm_accept(vg_batch* b, const double* d_e_new, double* d_state, double* d_poses,
+                           const double* d_cand, int32_t* d_accepted, double* d_e_hist, int32_t it,
+                           int32_t iters);
+
+}  // namespace vg

@@ -1,0 +1,297 @@
+"""Python binding of the VGICP C ABI (``include/vgicp.h``): argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module converts
+numpy arrays / torch tensors to pointers, orders the library's stream against
+torch's current stream for the ``*_async`` calls, and raises ``VGError`` on a
+non-zero status.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BatchOptions, PRECISIONS, check, load
+
+
+def _p(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _tp(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a if shape is None else a.reshape(shape)
+
+
+def poses12(poses) -> np.ndarray:
+    """(F, 4, 4) or (F, 12) or (4, 4) -> contiguous (F, 12) float64 [R row-major | t]."""
+    P = np.asarray(poses, dtype=np.float64)
+    if P.ndim == 2 and P.shape == (4, 4):
+        P = P[None]
+    if P.ndim == 3 and P.shape[1:] == (4, 4):
+        out = np.concatenate([P[:, :3, :3].reshape(-1, 9), P[:, :3, 3]], axis=1)
+    else:
+        out = P.reshape(-1, 12)
+    return np.ascontiguousarray(out)
+
+
+def pose4x4(p12) -> np.ndarray:
+    p = np.asarray(p12, dtype=np.float64).reshape(-1, 12)
+    T = np.tile(np.eye(4), (p.shape[0], 1, 1))
+    T[:, :3, :3] = p[:, :9].reshape(-1, 3, 3)
+    T[:, :3, 3] = p[:, 9:]
+    return T
+
+
+class Context:
+    """A device plus the HIP stream all library work is queued on."""
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        self.device = device
+        self.stream = torch.cuda.Stream(device=device)
+        h = C.c_void_p()
+        check(lib.vg_context_create(device, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            torch.cuda.synchronize(self.device)
+            check(load().vg_context_destroy(self.handle))
+            self.handle = None
+
+    # ordering against torch's current stream for device-pointer calls
+    def enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def leave(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def se3_retract(self, T0: torch.Tensor, xi: torch.Tensor, jacobian: bool = True):
+        """T = T0 Exp(xi) (F x 12 FP64) and the right Jacobian J_r(xi) (F x 6 x 6) on the device."""
+        F = T0.shape[0]
+        T0 = T0.contiguous().to(torch.float64)
+        xi = xi.contiguous().to(torch.float64)
+        T = torch.empty((F, 12), dtype=torch.float64, device=T0.device)
+        jr = torch.empty((F, 6, 6), dtype=torch.float64, device=T0.device) if jacobian else None
+        self.enter()
+        check(load().vg_se3_retract_async(self.handle, F, _tp(T0), _tp(xi), _tp(T), _tp(jr)))
+        self.leave()
+        return T, jr
+
+
+class VoxelMap:
+    """Multi-resolution Gaussian voxel map of a target cloud on the device."""
+
+    def __init__(self, ctx: Context, xyz, cov, resolutions):
+        xyz = _f64(xyz, (-1, 3))
+        cov = _f64(cov, (-1, 6))
+        res = _f64(resolutions, (-1,))
+        self.ctx = ctx
+        self.L = int(res.shape[0])
+        self.resolutions = res.tolist()
+        h = C.c_void_p()
+        check(load().vg_build_voxelmap(ctx.handle, _p(xyz), _p(cov), xyz.shape[0], _p(res), self.L, C.byref(h)))
+        self.handle = h
+
+    def info(self, level=0):
+        V, cap = C.c_int64(), C.c_int64()
+        check(load().vg_voxelmap_info(self.handle, level, C.byref(V), C.byref(cap)))
+        return V.value, cap.value
+
+    def export(self, level=0):
+        V, _ = self.info(level)
+        keys = np.zeros((max(V, 1), 3), dtype=np.int64)
+        means = np.zeros((max(V, 1), 3))
+        covs = np.zeros((max(V, 1), 6))
+        counts = np.zeros(max(V, 1), dtype=np.int64)
+        n = C.c_int64(max(V, 1))
+        check(load().vg_voxelmap_export(self.handle, level, C.byref(n), _p(keys), _p(means), _p(covs),
+                                        _p(counts)))
+        V = n.value
+        return keys[:V], means[:V], covs[:V], counts[:V]
+
+    def close(self):
+        if self.handle:
+            check(load().vg_voxelmap_destroy(self.handle))
+            self.handle = None
+
+
+class Source:
+    """A source Gaussian cloud on the device (internally Morton ordered)."""
+
+    def __init__(self, ctx: Context, xyz, cov, normals=None):
+        xyz = _f64(xyz, (-1, 3))
+        cov = _f64(cov, (-1, 6))
+        nrm = None if normals is None else _f64(normals, (-1, 3))
+        self.ctx = ctx
+        self.n = int(xyz.shape[0])
+        h = C.c_void_p()
+        check(load().vg_create_source(ctx.handle, _p(xyz), _p(cov), _p(nrm), self.n, C.byref(h)))
+        self.handle = h
+
+    def set_points(self, xyz: torch.Tensor):
+        """Replace positions from a device tensor (n x 3, float32 or float64, caller order)."""
+        assert xyz.is_cuda and xyz.shape == (self.n, 3)
+        t = xyz.contiguous()
+        dt = 0 if t.dtype == torch.float32 else 1
+        if t.dtype not in (torch.float32, torch.float64):
+            raise TypeError("points must be float32 or float64")
+        self.ctx.enter()
+        check(load().vg_source_set_points_async(self.handle, _tp(t), dt))
+        self.ctx.leave()
+        return t
+
+    def close(self):
+        if self.handle:
+            check(load().vg_source_destroy(self.handle))
+            self.handle = None
+
+
+class FactorBatch:
+    """F factors linearized together (one upload, one download per call)."""
+
+    def __init__(self, ctx: Context, sources, maps, viewpoints=None, precision="fp32c", validation=False,
+                 use_graph=True, plain=False, block=0, tile=0, blocks_per_cu=0, tune_cache=None):
+        lib = load()
+        self.ctx = ctx
+        self.sources = list(sources)
+        self.maps = list(maps)
+        F = len(self.sources)
+        assert F == len(self.maps) and F > 0
+        self.F = F
+        self.L = self.maps[0].L
+        self.precision = precision
+        o = BatchOptions()
+        o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        o.surface_validation = int(bool(validation))
+        o.use_graph = int(bool(use_graph))
+        o.plain_per_factor = int(bool(plain))
+        o.block_threads = int(block)
+        o.tile_points = int(tile)
+        o.blocks_per_cu = int(blocks_per_cu)
+        o.tune_cache = tune_cache.encode() if tune_cache else None
+        srcs = (C.c_void_p * F)(*[s.handle.value for s in self.sources])
+        tgts = (C.c_void_p * F)(*[m.handle.value for m in self.maps])
+        vp = None if viewpoints is None else _f64(viewpoints, (F, 3))
+        h = C.c_void_p()
+        check(lib.vg_create_factor_batch(ctx.handle, F, srcs, tgts, _p(vp), C.byref(o), C.byref(h)))
+        self.handle = h
+        # rows of the concatenated point gradient (sources in order of first use)
+        seen, self.grad_rows, self.source_rows = {}, 0, {}
+        for s in self.sources:
+            if id(s) not in seen:
+                seen[id(s)] = self.grad_rows
+                self.source_rows[id(s)] = (self.grad_rows, s.n)
+                self.grad_rows += s.n
+
+    def info(self):
+        tp, nt = C.c_int64(), C.c_int64()
+        bl, ti, gr = C.c_int32(), C.c_int32(), C.c_int32()
+        check(load().vg_batch_info(self.handle, C.byref(tp), C.byref(nt), C.byref(bl), C.byref(ti), C.byref(gr)))
+        return {"total_points": tp.value, "n_tiles": nt.value, "block_threads": bl.value,
+                "tile_points": ti.value, "grid_blocks": gr.value}
+
+    def linearize(self, poses):
+        P = poses12(poses)
+        assert P.shape[0] == self.F
+        e = np.zeros(self.F)
+        H = np.zeros((self.F, 6, 6))
+        b = np.zeros((self.F, 6))
+        inl = np.zeros((self.F, self.L), dtype=np.int64)
+        check(load().vg_linearize(self.handle, _p(P), _p(e), _p(H), _p(b), _p(inl)))
+        return e, H, b, inl
+
+    def evaluate(self, poses):
+        P = poses12(poses)
+        e = np.zeros(self.F)
+        check(load().vg_evaluate(self.handle, _p(P), _p(e)))
+        return e
+
+    def linearize_async(self, d_poses: torch.Tensor):
+        d_poses = d_poses.contiguous()
+        out = torch.empty((self.F, 43), dtype=torch.float64, device=d_poses.device)
+        inl = torch.empty((self.F, self.L), dtype=torch.int64, device=d_poses.device)
+        self.ctx.enter()
+        check(load().vg_linearize_async(self.handle, _tp(d_poses), _tp(out), _tp(inl)))
+        self.ctx.leave()
+        return out, inl
+
+    def evaluate_async(self, d_poses: torch.Tensor):
+        d_poses = d_poses.contiguous()
+        e = torch.empty(self.F, dtype=torch.float64, device=d_poses.device)
+        self.ctx.enter()
+        check(load().vg_evaluate_async(self.handle, _tp(d_poses), _tp(e)))
+        self.ctx.leave()
+        return e
+
+    def backward_async(self, d_poses: torch.Tensor, grad_e: torch.Tensor, jr=None, points_dtype=None):
+        """(grad_xi F x 6 FP64, grad_points grad_rows x 3 or None)."""
+        d_poses = d_poses.contiguous()
+        grad_e = grad_e.contiguous().to(torch.float64)
+        gxi = torch.empty((self.F, 6), dtype=torch.float64, device=d_poses.device)
+        gp = None
+        dt = 0
+        if points_dtype is not None:
+            gp = torch.empty((self.grad_rows, 3), dtype=points_dtype, device=d_poses.device)
+            dt = 0 if points_dtype == torch.float32 else 1
+        jr_c = None if jr is None else jr.contiguous()
+        self.ctx.enter()
+        check(load().vg_backward_async(self.handle, _tp(d_poses), _tp(grad_e), _tp(jr_c), _tp(gxi), _tp(gp), dt))
+        self.ctx.leave()
+        return gxi, gp
+
+    def lm(self, poses, iters=10, lambda0=1e-4):
+        P = poses12(poses)
+        out = np.zeros_like(P)
+        acc = np.zeros((self.F, iters), dtype=np.int32)
+        eh = np.zeros((self.F, iters))
+        check(load().vg_lm_run(self.handle, _p(P), iters, float(lambda0), _p(out), _p(acc), _p(eh)))
+        return pose4x4(out), acc.astype(bool), eh
+
+    def correspondences(self, pose, factor):
+        P = poses12(pose)[0]
+        n = self.sources[factor].n
+        keys = np.zeros((max(n, 1), self.L, 3), dtype=np.int64)
+        found = np.zeros((max(n, 1), self.L), dtype=np.int32)
+        check(load().vg_correspondences(self.handle, _p(P), int(factor), _p(keys), _p(found)))
+        return keys[:n], found[:n]
+
+    def tune(self, poses, reps=3):
+        P = poses12(poses)
+        ch = np.zeros(3, dtype=np.int32)
+        check(load().vg_batch_tune(self.handle, _p(P), int(reps), _p(ch)))
+        return {"block_threads": int(ch[0]), "tile_points": int(ch[1]), "blocks_per_cu": int(ch[2])}
+
+    def time_kernels(self, poses, reps=10):
+        P = poses12(poses)
+        ms = np.zeros(3, dtype=np.float32)
+        check(load().vg_batch_time_kernels(self.handle, _p(P), int(reps), _p(ms)))
+        return {"tile_kernel_ms": float(ms[0]), "reduce_ms": float(ms[1]), "call_ms": float(ms[2])}
+
+    def close(self):
+        if self.handle:
+            check(load().vg_batch_destroy(self.handle))
+            self.handle = None
+
+
+def build_workload(ctx: Context, cfg: dict, precision="fp32c", validation=False, use_graph=True, plain=False,
+                   **shape):
+    """Device objects for a ``synth`` workload dict: (maps, sources, batch)."""
+    res = cfg["resolutions"]
+    tgt_ids = sorted({t for (_, t) in cfg["factors"]})
+    src_ids = sorted({s for (s, _) in cfg["factors"]})
+    maps = {t: VoxelMap(ctx, cfg["targets"][t].xyz64(), cfg["targets"][t].cov64(), res) for t in tgt_ids}
+    srcs = {s: Source(ctx, cfg["sources"][s].xyz64(), cfg["sources"][s].cov64(), cfg["sources"][s].nrm64())
+            for s in src_ids}
+    batch = FactorBatch(ctx, [srcs[s] for (s, _) in cfg["factors"]], [maps[t] for (_, t) in cfg["factors"]],
+                        viewpoints=np.asarray(cfg["target_viewpoints"]), precision=precision,
+                        validation=validation, use_graph=use_graph, plain=plain, **shape)
+    return maps, srcs, batch

@@ -1,0 +1,93 @@
+"""Comparison of device results with the FP64 oracle.
+
+Correspondences: voxel keys must be bit-identical except for points whose FP64
+transformed position lies within ``band`` (1e-5 m) of a face of its voxel;
+those are counted, and for them either neighbouring voxel is a correct answer.
+The expected e/H/b is the oracle's, with the contribution of every such point
+whose device key differs replaced by the oracle's own terms for the device's
+key (both terms come from the oracle).
+
+Relative errors: e |e - e*| / |e*|, H ||H - H*||_F / ||H*||_F, b ||b - b*|| / ||b*||.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+BAND = 1e-5
+REL = 1e-5
+
+
+def rel_err(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return 0.0 if np.linalg.norm(a) == 0.0 else np.inf
+    return float(np.linalg.norm(a - b) / nb)
+
+
+def visibility_margin(ofac, pose):
+    """|(mu - T^-1 c) . n| per point, FP64 (the quantity the visibility rule thresholds at 0)."""
+    T = np.asarray(pose)
+    R, t = T[:3, :3], T[:3, 3]
+    cs = R.T @ (ofac.viewpoint - t)
+    return np.abs(np.einsum("ni,ni->n", ofac.xyz - cs[None], ofac.nrm))
+
+
+def expected_with_device_keys(ofac, pose, keys_dev, found_dev, band=BAND, vis_band=1e-4):
+    """Oracle e/H/b with ambiguous points resolved the way the device resolved them.
+
+    Returns (e, H, b, stats) and asserts every unambiguous key is identical.
+    """
+    tr = ofac.linearize(pose, trace=True)
+    keys_o, vidx_o, face, vis_o = tr["keys"], tr["vidx"], tr["face"], tr["visible"]
+    n, L = vidx_o.shape
+    e, H, b = tr["e"], tr["H"].copy(), tr["b"].copy()
+    near = face < band
+    mism = np.any(keys_dev != keys_o, axis=2)
+    bad = mism & ~near
+    assert not bad.any(), "device keys differ from the oracle away from voxel faces: %d cases, e.g. %s" % (
+        int(bad.sum()), list(zip(*np.nonzero(bad)))[:5])
+    # visibility: -1 from the device means discarded
+    vis_dev = ~np.all(found_dev == -1, axis=1) if L else np.ones(n, bool)
+    vis_flip = vis_dev != vis_o
+    if vis_flip.any():
+        marg = visibility_margin(ofac, pose)
+        assert np.all(marg[vis_flip] < vis_band), "visibility differs away from the tie"
+    # found flags must agree where keys agree and the point is visible on both sides
+    both = vis_dev & vis_o
+    fo = (vidx_o >= 0)
+    fd = (found_dev == 1)
+    same_key = ~mism
+    agree = fo[both[:, None] & same_key] == fd[both[:, None] & same_key] if n else np.array([True])
+    assert np.all(agree), "found flags differ for identical keys"
+    adjusted = 0
+    todo = np.nonzero(mism | vis_flip[:, None])
+    for k, l in zip(*todo):
+        own_used = vis_o[k] and vidx_o[k, l] >= 0
+        dev_used = vis_dev[k] and found_dev[k, l] == 1
+        if own_used:
+            ok, e1, H1, b1 = ofac.point_terms(pose, k, l, keys_o[k, l])
+            e -= e1
+            H -= H1
+            b -= b1
+        if dev_used:
+            ok, e2, H2, b2 = ofac.point_terms(pose, k, l, keys_dev[k, l])
+            assert ok
+            e += e2
+            H += H2
+            b += b2
+        adjusted += 1
+    stats = {"near_face": int(near.sum()), "near_face_mismatch": int((mism & near).sum()),
+             "visibility_flips": int(vis_flip.sum()), "adjusted": adjusted,
+             "inliers_oracle": tr["inliers"].tolist()}
+    return e, H, b, stats
+
+
+def check_factor(batch, f, pose, ofac, e_dev, H_dev, b_dev, rel=REL):
+    keys_dev, found_dev = batch.correspondences(pose, f)
+    e, H, b, stats = expected_with_device_keys(ofac, pose, keys_dev, found_dev)
+    errs = {"e": rel_err(e_dev, e), "H": rel_err(H_dev, H), "b": rel_err(b_dev, b)}
+    assert errs["e"] <= rel and errs["H"] <= rel and errs["b"] <= rel, (errs, stats)
+    return errs, stats

@@ -1,0 +1,252 @@
+"""Device parity against the FP64 oracle through the C ABI (needs an MI355X).
+
+Bar: voxel keys / correspondences bit-exact outside the 1e-5 m face band,
+voxel statistics bit-exact in FP64, e/H/b within relative 1e-5 for the
+FP32-compensated mode (and 1e-10 for the FP64 mode), batched == plain ==
+graph replay bitwise, and replays deterministic.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import REL, check_factor, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vg():
+    from paper_2407_10344_amd import vgicp
+    ctx = vgicp.Context(0)
+    yield vgicp, ctx
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return synth.config1(seed=1)
+
+
+def oracle_factor(cfg, f, validate=False):
+    s, t = cfg["factors"][f]
+    return oracle.factor_from_clouds(cfg["sources"][s], cfg["targets"][t], cfg["resolutions"],
+                                     viewpoint=cfg["target_viewpoints"][f], validate=validate)
+
+
+# ----------------------------------------------------------------- voxel map build
+
+@pytest.mark.parametrize("res", [(0.5,), (0.25, 0.5, 1.0, 2.0)])
+def test_voxelmap_matches_oracle_bit_exact(vg, c1, res):
+    vgicp, ctx = vg
+    t = c1["targets"][0]
+    m = vgicp.VoxelMap(ctx, t.xyz64(), t.cov64(), list(res))
+    for l, r in enumerate(res):
+        k_o, m_o, c_o, n_o = oracle.voxelize(t.xyz64(), t.cov64(), r)
+        k_d, m_d, c_d, n_d = m.export(l)
+        print("level", l, "voxels", len(k_o), flush=True)
+        assert np.array_equal(k_d, k_o)
+        assert np.array_equal(n_d, n_o)
+        assert np.array_equal(m_d, m_o)     # same FP64 summation order -> identical bits
+        assert np.array_equal(c_d, c_o)
+        V, cap = m.info(l)
+        assert V == len(k_o) and cap >= 2 * V
+    m.close()
+
+
+# ----------------------------------------------------------------- single factor
+
+@pytest.mark.parametrize("which", ["init", "true"])
+def test_config1_linearize(vg, c1, which):
+    vgicp, ctx = vg
+    maps, srcs, batch = vgicp.build_workload(ctx, c1)
+    pose = c1["poses"][0] if which == "init" else c1["poses_true"][0]
+    e, H, b, inl = batch.linearize([pose])
+    of = oracle_factor(c1, 0)
+    errs, stats = check_factor(batch, 0, pose, of, e[0], H[0], b[0])
+    print("config1", which, errs, stats, flush=True)
+    assert inl[0].tolist() == of.linearize(pose)["inliers"].tolist() or stats["adjusted"] > 0
+    batch.close()
+
+
+def test_config1_evaluate(vg, c1):
+    vgicp, ctx = vg
+    maps, srcs, batch = vgicp.build_workload(ctx, c1)
+    of = oracle_factor(c1, 0)
+    for pose in (c1["poses"][0], c1["poses_true"][0]):
+        e = batch.evaluate([pose])
+        assert rel_err(e[0], of.evaluate(pose)) <= REL
+    batch.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-3)])
+def test_config1_other_precisions(vg, c1, prec, tol):
+    vgicp, ctx = vg
+    maps, srcs, batch = vgicp.build_workload(ctx, c1, precision=prec)
+    pose = c1["poses_true"][0]
+    e, H, b, _ = batch.linearize([pose])
+    of = oracle_factor(c1, 0)
+    if prec == "fp64":
+        errs, stats = check_factor(batch, 0, pose, of, e[0], H[0], b[0], rel=tol)
+    else:
+        r = of.linearize(pose)
+        errs = {"e": rel_err(e[0], r["e"]), "H": rel_err(H[0], r["H"]), "b": rel_err(b[0], r["b"])}
+        assert max(errs.values()) < tol, errs
+    print(prec, errs, flush=True)
+    batch.close()
+
+
+# ----------------------------------------------------------------- odometry batch, 4 levels
+
+@pytest.fixture(scope="module")
+def c2():
+    return synth.config2(seed=2)
+
+
+def test_config2_batch(vg, c2):
+    vgicp, ctx = vg
+    maps, srcs, batch = vgicp.build_workload(ctx, c2)
+    poses = np.array(c2["poses"])
+    e, H, b, inl = batch.linearize(poses)
+    worst = {"e": 0, "H": 0, "b": 0}
+    for f in range(len(poses)):
+        of = oracle_factor(c2, f)
+        errs, stats = check_factor(batch, f, poses[f], of, e[f], H[f], b[f])
+        worst = {k: max(worst[k], errs[k]) for k in worst}
+    print("config2 worst", worst, flush=True)
+    # plain per-factor path and graph replay give bitwise identical results
+    _, _, plain = vgicp.build_workload(ctx, c2, plain=True, use_graph=False)
+    e2, H2, b2, inl2 = plain.linearize(poses)
+    assert np.array_equal(e, e2) and np.array_equal(H, H2) and np.array_equal(b, b2) and np.array_equal(inl, inl2)
+    for _ in range(3):
+        e3, H3, b3, _ = batch.linearize(poses)
+        assert np.array_equal(e, e3) and np.array_equal(H, H3) and np.array_equal(b, b3)
+    plain.close()
+    batch.close()
+
+
+def test_batch_is_concatenation_of_singles(vg, c2):
+    vgicp, ctx = vg
+    maps, srcs, batch = vgicp.build_workload(ctx, c2)
+    poses = np.array(c2["poses"])
+    e, H, b, _ = batch.linearize(poses)
+    for f in (0, 7, 19):
+        s, t = c2["factors"][f]
+        single = vgicp.FactorBatch(ctx, [srcs[s]], [maps[t]], precision="fp32c")
+        e1, H1, b1, _ = single.linearize(poses[f:f + 1])
+        assert np.array_equal(e1[0], e[f]) and np.array_equal(H1[0], H[f]) and np.array_equal(b1[0], b[f])
+        single.close()
+    batch.close()
+
+
+# ----------------------------------------------------------------- edge cases
+
+def test_ragged_and_tiny_sources(vg, c1):
+    """Sources of 1, 63, 64, 65 and 2050 points (ragged chunk and tile tails)."""
+    vgicp, ctx = vg
+    t = c1["targets"][0]
+    s = c1["sources"][0]
+    m = vgicp.VoxelMap(ctx, t.xyz64(), t.cov64(), [0.5])
+    ovm = oracle.VoxelMap(t.xyz64(), t.cov64(), [0.5])
+    pose = c1["poses_true"][0]
+    for n in (1, 63, 64, 65, 2050):
+        sub = s.subset(np.arange(n))
+        src = vgicp.Source(ctx, sub.xyz64(), sub.cov64(), sub.nrm64())
+        for tile in (64, 1024):
+            batch = vgicp.FactorBatch(ctx, [src], [m], tile=tile, block=128)
+            e, H, b, inl = batch.linearize([pose])
+            of = oracle.Factor(sub.xyz64(), sub.cov64(), ovm)
+            r = of.linearize(pose)
+            if r["inliers"][0] == 0:
+                assert e[0] == 0.0 and np.all(H[0] == 0) and np.all(b[0] == 0)
+            else:
+                check_factor(batch, 0, pose, of, e[0], H[0], b[0])
+            batch.close()
+        src.close()
+    m.close()
+
+
+def test_empty_source_and_empty_map(vg, c1):
+    vgicp, ctx = vg
+    t = c1["targets"][0]
+    s = c1["sources"][0]
+    m = vgicp.VoxelMap(ctx, t.xyz64(), t.cov64(), [0.5])
+    empty_m = vgicp.VoxelMap(ctx, np.zeros((0, 3)), np.zeros((0, 6)), [0.5])
+    src = vgicp.Source(ctx, s.xyz64(), s.cov64())
+    empty_s = vgicp.Source(ctx, np.zeros((0, 3)), np.zeros((0, 6)))
+    batch = vgicp.FactorBatch(ctx, [empty_s, src, src], [m, empty_m, m])
+    e, H, b, inl = batch.linearize([np.eye(4)] * 3)
+    assert e[0] == 0 and e[1] == 0 and np.all(H[:2] == 0) and np.all(b[:2] == 0)
+    assert inl[0, 0] == 0 and inl[1, 0] == 0 and inl[2, 0] > 0
+    batch.close()
+    for x in (src, empty_s, m, empty_m):
+        x.close()
+
+
+def test_zero_residual_lattice(vg):
+    """Identical one-point-per-voxel clouds at identity: the residual vanishes.
+
+    FP64 mode reproduces e = 0 and b = 0 exactly.  The compensated mode stores
+    each point as an FP32 offset from its 64-point chunk anchor, which can drop
+    the last bit of a coordinate, so there e and b are zero to that rounding.
+    """
+    vgicp, ctx = vg
+    cloud, res = synth.tiny_lattice_pair(0)
+    m = vgicp.VoxelMap(ctx, cloud.xyz64(), cloud.cov64(), res)
+    src = vgicp.Source(ctx, cloud.xyz64(), cloud.cov64())
+    of = oracle.Factor(cloud.xyz64(), cloud.cov64(), oracle.VoxelMap(cloud.xyz64(), cloud.cov64(), res))
+    H_o = of.linearize(np.eye(4))["H"]
+    for prec in ("fp64", "fp32c"):
+        batch = vgicp.FactorBatch(ctx, [src], [m], precision=prec)
+        e, H, b, inl = batch.linearize([np.eye(4)])
+        assert inl[0].tolist() == [cloud.n] * len(res)
+        if prec == "fp64":
+            assert e[0] == 0.0 and np.all(b[0] == 0.0)
+        else:
+            # offsets rounded by at most 2^-24 relative of a few metres
+            assert e[0] < 1e-9 and np.linalg.norm(b[0]) < 1e-6 * np.linalg.norm(H_o)
+        assert rel_err(H[0], H_o) <= REL
+        batch.close()
+    src.close()
+    m.close()
+
+
+def test_surface_validation(vg, c1):
+    vgicp, ctx = vg
+    maps, srcs, batch = vgicp.build_workload(ctx, c1, validation=True)
+    for pose in (c1["poses"][0], c1["poses_true"][0]):
+        e, H, b, inl = batch.linearize([pose])
+        of = oracle_factor(c1, 0, validate=True)
+        errs, stats = check_factor(batch, 0, pose, of, e[0], H[0], b[0])
+        print("validation", errs, stats, flush=True)
+        assert of.linearize(pose)["inliers"][0] < oracle_factor(c1, 0).linearize(pose)["inliers"][0]
+    batch.close()
+
+
+def test_invalid_arguments(vg, c1):
+    vgicp, ctx = vg
+    from paper_2407_10344_amd._lib import VGError
+    t = c1["targets"][0]
+    with pytest.raises(VGError, match="INVALID_ARG"):
+        vgicp.VoxelMap(ctx, t.xyz64(), t.cov64(), [0.3])           # not a power of two
+    bad = t.cov64().copy()
+    bad[5] = [1, 2, 0, 1, 0, 1]                                    # not SPD
+    with pytest.raises(VGError, match="NOT_SPD"):
+        vgicp.VoxelMap(ctx, t.xyz64(), bad, [0.5])
+    far = t.xyz64().copy()
+    far[3] += 1e5                                                  # beyond the key range
+    with pytest.raises(VGError, match="KEY_RANGE"):
+        vgicp.VoxelMap(ctx, far, t.cov64(), [0.5])
+    maps, srcs, batch = vgicp.build_workload(ctx, c1)
+    P = np.eye(4)
+    P[0, 0] = np.nan
+    with pytest.raises(VGError, match="INVALID_ARG"):
+        batch.linearize([P])
+    P = np.eye(4)
+    P[:3, :3] *= 1.01
+    with pytest.raises(VGError, match="orthonormal"):
+        batch.linearize([P])
+    with pytest.raises(VGError, match="STATE"):
+        list(maps.values())[0].close()                             # still used by the batch
+    batch.close()

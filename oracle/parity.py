@@ -1,4 +1,4 @@
-"""Comparison of device results with the FP64 oracle.
+"""Comparison of device results with the FP64 oracle (test infrastructure).
 
 Correspondences: voxel keys must be bit-identical except for points whose FP64
 transformed position lies within ``band`` (1e-5 m) of a face of its voxel;

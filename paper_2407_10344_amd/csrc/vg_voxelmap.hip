@@ -260,13 +260,7 @@ __global__ void k_layout(const double* __restrict__ xyz, const double* __restric
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_pad) return;
     const int64_t c = i / kChunk;
-    const int64_t a = sorted_idx[c * kChunk];
-    const double an[3] = {xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2]};
-    if ((i % kChunk) == 0) {
-        anchor[3 * c + 0] = an[0];
-        anchor[3 * c + 1] = an[1];
-        anchor[3 * c + 2] = an[2];
-    }
+    const double an[3] = {anchor[3 * c + 0], anchor[3 * c + 1], anchor[3 * c + 2]};
     if (i < n) {
         const int64_t s = sorted_idx[i];
         perm[i] = (int32_t)s;
@@ -306,6 +300,27 @@ __global__ void k_layout(const double* __restrict__ xyz, const double* __restric
     }
 }
 
+// Anchor of each 64-point chunk: the centroid of its points (keeps the FP32
+// offsets, and so their rounding, as small as the chunk allows).
+__global__ void k_anchors(const double* __restrict__ xyz, const int32_t* __restrict__ sorted_idx, int64_t n,
+                          int64_t n_chunks, double* __restrict__ anchor) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chunks) return;
+    const int64_t i0 = c * kChunk;
+    const int64_t i1 = (i0 + kChunk < n) ? i0 + kChunk : n;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = i0; i < i1; ++i) {
+        const int64_t p = sorted_idx[i];
+        s[0] += xyz[3 * p + 0];
+        s[1] += xyz[3 * p + 1];
+        s[2] += xyz[3 * p + 2];
+    }
+    const double inv = 1.0 / (double)(i1 - i0);
+    anchor[3 * c + 0] = s[0] * inv;
+    anchor[3 * c + 1] = s[1] * inv;
+    anchor[3 * c + 2] = s[2] * inv;
+}
+
 vg_status layout_source(vg_context* ctx, vg_source* s, const double* d_xyz, const double* d_cov,
                         const double* d_nrm) {
     hipStream_t st = ctx->stream;
@@ -331,6 +346,8 @@ vg_status layout_source(vg_context* ctx, vg_source* s, const double* d_xyz, cons
         if ((e = hipcub::DeviceRadixSort::SortPairs(tmp, tb2, codes, codes2, idx, idx2, (int)n, 0, 63, st)) !=
             hipSuccess)
             break;
+        k_anchors<<<grid_of(s->n_chunks), 256, 0, st>>>(d_xyz, idx2, n, s->n_chunks, s->anchor);
+        if ((e = hipGetLastError()) != hipSuccess) break;
         k_layout<<<grid_of(n_pad), 256, 0, st>>>(d_xyz, d_cov, d_nrm, idx2, n, n_pad, s->dxyz, s->cov, s->nrm,
                                                  s->anchor, s->axyz, s->xyz64, s->cov64, s->nrm64, s->perm);
         if ((e = hipGetLastError()) != hipSuccess) break;

@@ -49,12 +49,43 @@ class Cloud:
 
 
 def smallest_eigvec(cov3: np.ndarray) -> np.ndarray:
-    """Unit eigenvectors of the smallest eigenvalue of a stack of 3x3 SPD matrices."""
-    out = np.empty((cov3.shape[0], 3))
-    step = 1 << 20
-    for s in range(0, cov3.shape[0], step):
-        _, v = np.linalg.eigh(cov3[s:s + step])
-        out[s:s + step] = v[:, :, 0]
+    """Unit eigenvectors of the smallest eigenvalue of a stack of 3x3 symmetric matrices.
+
+    Closed form: the eigenvalue from the trigonometric solution of the
+    characteristic cubic, the vector as the longest cross product of two rows
+    of (A - lambda I).  Falls back to numpy.linalg.eigh for the rare rows where
+    that cross product is tiny (near-repeated smallest eigenvalue).
+    """
+    a, b, c = cov3[:, 0, 0], cov3[:, 1, 1], cov3[:, 2, 2]
+    d, e, f = cov3[:, 0, 1], cov3[:, 0, 2], cov3[:, 1, 2]
+    q = (a + b + c) / 3.0
+    p1 = d * d + e * e + f * f
+    p2 = (a - q) ** 2 + (b - q) ** 2 + (c - q) ** 2 + 2.0 * p1
+    p = np.sqrt(np.maximum(p2 / 6.0, 1e-300))
+    ba, bb, bc = (a - q) / p, (b - q) / p, (c - q) / p
+    bd, be, bf = d / p, e / p, f / p
+    detB = ba * (bb * bc - bf * bf) - bd * (bd * bc - bf * be) + be * (bd * bf - bb * be)
+    r = np.clip(detB / 2.0, -1.0, 1.0)
+    phi = np.arccos(r) / 3.0
+    lam = q + 2.0 * p * np.cos(phi + 2.0 * np.pi / 3.0)
+    r0 = np.stack([a - lam, d, e], axis=1)
+    r1 = np.stack([d, b - lam, f], axis=1)
+    r2 = np.stack([e, f, c - lam], axis=1)
+    c01 = np.cross(r0, r1)
+    c02 = np.cross(r0, r2)
+    c12 = np.cross(r1, r2)
+    n01 = np.einsum("ni,ni->n", c01, c01)
+    n02 = np.einsum("ni,ni->n", c02, c02)
+    n12 = np.einsum("ni,ni->n", c12, c12)
+    best = np.where(n01 >= n02, np.where(n01 >= n12, 0, 2), np.where(n02 >= n12, 1, 2))
+    v = np.where((best == 0)[:, None], c01, np.where((best == 1)[:, None], c02, c12))
+    nv = np.sqrt(np.maximum(np.maximum(n01, n02), n12))
+    scale = np.maximum(p, 1e-300) ** 2
+    bad = nv < 1e-6 * scale
+    out = v / np.where(nv > 0, nv, 1.0)[:, None]
+    if bad.any():
+        _, w = np.linalg.eigh(cov3[bad])
+        out[bad] = w[:, :, 0]
     return out
 
 

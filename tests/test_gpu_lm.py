@@ -1,0 +1,82 @@
+"""Device-resident Levenberg-Marquardt against the FP64 oracle's LM (needs an MI355X).
+
+Both run the same schedule (lambda0 = 1e-4, Marquardt damping diag(H),
+x10 / /10, fixed iteration count, accept on a lower error), so the accept
+sequences must agree and the final poses must agree to the precision of the
+mode: FP64 to 1e-9, FP32-compensated to 1e-5 (rotation in rad, translation in m).
+"""
+
+import numpy as np
+import pytest
+from scipy.linalg import logm
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vg():
+    from paper_2407_10344_amd import vgicp
+    ctx = vgicp.Context(0)
+    yield vgicp, ctx
+    ctx.close()
+
+
+def pose_error(Ta, Tb):
+    D = np.linalg.inv(Ta) @ Tb
+    c = np.clip((np.trace(D[:3, :3]) - 1) / 2, -1.0, 1.0)
+    return float(np.arccos(c)), float(np.linalg.norm(D[:3, 3]))
+
+
+@pytest.fixture(scope="module")
+def lm_case():
+    cfg = synth.config1(seed=21, n_target=20000, n_source=8000, resolutions=(0.5, 1.0, 2.0), angle_deg=2.0,
+                        trans_m=0.2)
+    of = oracle.factor_from_clouds(cfg["sources"][0], cfg["targets"][0], cfg["resolutions"])
+    ref = of.lm(cfg["poses"][0], iters=10, lambda0=1e-4)
+    return cfg, ref
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32c", 1e-5)])
+def test_lm_matches_oracle(vg, lm_case, prec, tol):
+    vgicp, ctx = vg
+    cfg, ref = lm_case
+    maps, srcs, batch = vgicp.build_workload(ctx, cfg, precision=prec)
+    T, acc, eh = batch.lm([cfg["poses"][0]], iters=10, lambda0=1e-4)
+    rot, tr = pose_error(ref["pose"], T[0])
+    print(prec, "accepted", acc[0].astype(int).tolist(), "oracle", ref["accepted"].astype(int).tolist(),
+          "pose diff rad %.3g m %.3g" % (rot, tr), flush=True)
+    assert acc[0].tolist() == ref["accepted"].tolist()
+    assert rot < tol and tr < tol
+    np.testing.assert_allclose(eh[0], ref["e"], rtol=1e-5)
+    # it moved toward the true pose
+    r0 = pose_error(cfg["poses_true"][0], cfg["poses"][0])
+    r1 = pose_error(cfg["poses_true"][0], T[0])
+    assert r1[0] + r1[1] < r0[0] + r0[1]
+    batch.close()
+
+
+@pytest.mark.slow
+def test_precision_stress_10km(vg):
+    """4 factors of 1M points 10 km from the origin: naive FP32, compensated FP32 and FP64
+    each drive a 10-iteration LM; pose error against the FP64 oracle's LM."""
+    vgicp, ctx = vg
+    cfg = synth.config5()
+    res = {}
+    refs = []
+    for f in range(len(cfg["factors"])):
+        of = oracle.factor_from_clouds(cfg["sources"][f], cfg["targets"][f], cfg["resolutions"])
+        refs.append(of.lm(cfg["poses"][f], iters=10, lambda0=1e-4))
+    for prec in ("fp32", "fp32c", "fp64"):
+        maps, srcs, batch = vgicp.build_workload(ctx, cfg, precision=prec)
+        T, acc, eh = batch.lm(np.array(cfg["poses"]), iters=10, lambda0=1e-4)
+        errs = [pose_error(refs[f]["pose"], T[f]) for f in range(len(refs))]
+        res[prec] = (max(e[0] for e in errs), max(e[1] for e in errs))
+        print(prec, "max pose error vs oracle: rot %.3g rad, trans %.3g m" % res[prec], flush=True)
+        batch.close()
+        for x in list(maps.values()) + list(srcs.values()):
+            x.close()
+    assert res["fp64"][0] < 1e-9 and res["fp64"][1] < 1e-8
+    assert res["fp32c"][0] < 1e-5 and res["fp32c"][1] < 1e-4

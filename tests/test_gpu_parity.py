@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from parity import REL, check_factor, rel_err
+from oracle.parity import REL, check_factor, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -220,7 +220,11 @@ def test_surface_validation(vg, c1):
         of = oracle_factor(c1, 0, validate=True)
         errs, stats = check_factor(batch, 0, pose, of, e[0], H[0], b[0])
         print("validation", errs, stats, flush=True)
-        assert of.linearize(pose)["inliers"][0] < oracle_factor(c1, 0).linearize(pose)["inliers"][0]
+        n_val = of.linearize(pose)["inliers"][0]
+        n_all = oracle_factor(c1, 0).linearize(pose)["inliers"][0]
+        assert n_val <= n_all
+        if pose is c1["poses"][0]:
+            assert n_val < n_all     # some points face away from the target viewpoint
     batch.close()
 
 

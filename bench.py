@@ -144,6 +144,7 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: library default / tuned)")
     ap.add_argument("--tile", type=int, default=0, help="source points per tile (0: default / tuned)")
     ap.add_argument("--bpc", type=int, default=0, help="persistent workgroups per CU (0: default / tuned)")
+    ap.add_argument("--lane-kahan", action="store_true", help="Kahan-compensated FP32 sums inside each lane")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many batched steps (for profilers), print nothing else")
@@ -160,7 +161,8 @@ def main():
     ctx = vgicp.Context(0)
     t = time.time()
     shape = {"block": args.block, "tile": args.tile, "blocks_per_cu": args.bpc}
-    maps, srcs, batch = vgicp.build_workload(ctx, cfg, precision=args.precision, use_graph=True, **shape)
+    maps, srcs, batch = vgicp.build_workload(ctx, cfg, precision=args.precision, use_graph=True,
+                                             lane_kahan=args.lane_kahan, **shape)
     torch.cuda.synchronize()
     log("device maps/sources/batch built in %.1f s" % (time.time() - t))
     poses = vgicp.poses12(np.array(cfg["poses"]))
@@ -233,7 +235,8 @@ def main():
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": dict(desc, precision=args.precision, total_source_points=pts, inlier_pairs=hits,
+        "config": dict(desc, precision=args.precision, lane_kahan=bool(args.lane_kahan),
+                       total_source_points=pts, inlier_pairs=hits,
                        hit_rate=hits / max(pts, 1), launch=info),
         "plain": None if plain_rate is None else {"value": plain_rate, "unit": "source points/s",
                                                   "batched_speedup": value / plain_rate},

@@ -65,8 +65,9 @@ typedef enum {
 } vg_status;
 
 typedef enum {
-    VG_FP32_COMPENSATED = 0, /* FP32 per point in re-centred coordinates, Kahan per lane,
-                                FP64 across waves, tiles and factors (the default) */
+    VG_FP32_COMPENSATED = 0, /* FP32 terms in re-centred coordinates; residual and fused
+                                covariance formed in FP64; FP64 sums across lanes, waves,
+                                tiles and factors (the default) */
     VG_FP32 = 1,             /* absolute FP32 coordinates, FP32 accumulation end to end */
     VG_FP64 = 2              /* FP64 data and arithmetic throughout */
 } vg_precision;
@@ -90,6 +91,8 @@ typedef struct {
     int32_t block_threads;      /* 64, 128, 256 or 512 threads per workgroup; 0 = default */
     int32_t tile_points;        /* source points per work tile, a multiple of 64; 0 = default */
     int32_t blocks_per_cu;      /* persistent workgroups per compute unit; 0 = default */
+    int32_t lane_kahan;         /* VG_FP32_COMPENSATED only: 1 = Kahan-compensated FP32 sums
+                                   inside each lane (sums above a lane are FP64 either way) */
     const char* tune_cache;     /* NULL: no autotuning.  Otherwise a file path: tuned shapes
                                    are read from it, or measured and appended to it */
 } vg_batch_options;

@@ -49,6 +49,7 @@ class BatchOptions(C.Structure):
         ("block_threads", C.c_int32),
         ("tile_points", C.c_int32),
         ("blocks_per_cu", C.c_int32),
+        ("lane_kahan", C.c_int32),
         ("tune_cache", C.c_char_p),
     ]
 

@@ -443,7 +443,11 @@ void fill_factor(vg_batch* b, int64_t f, const double* viewpoints) {
         q.inv_r = (float)(1.0 / lv.r);
         q.r64 = lv.r;
         q.inv_r64 = 1.0 / lv.r;
-        for (int a = 0; a < 3; ++a) q.K0[a] = lv.K0[a];
+        for (int a = 0; a < 3; ++a) {
+            q.K0[a] = lv.K0[a];
+            q.kmin[a] = lv.kmin[a];
+            q.kmax[a] = lv.kmax[a];
+        }
     }
     b->h_fac[f] = d;
 }
@@ -535,13 +539,13 @@ bool valid_shape(int block, int tile, int bpc) {
 
 vg_status run_linearize_device(vg_batch* b, const double* d_poses, double* d_out, int64_t* d_inl) {
     const int32_t nt = (int32_t)b->h_tiles.size();
-    VG_TRY(launch_tiles(b, kLin, d_poses, 0, nt, b->grid, nullptr, nullptr, 0));
+    VG_TRY(launch_tiles(b, kLin, d_poses, 0, nt, b->grid, nullptr, nullptr, 0, 0, b->F));
     return launch_reduce(b, kLin, d_poses, 0, (int32_t)b->F, d_out, d_inl, nullptr, nullptr, nullptr);
 }
 
 vg_status run_evaluate_device(vg_batch* b, const double* d_poses, double* d_e) {
     const int32_t nt = (int32_t)b->h_tiles.size();
-    VG_TRY(launch_tiles(b, kEval, d_poses, 0, nt, b->grid, nullptr, nullptr, 0));
+    VG_TRY(launch_tiles(b, kEval, d_poses, 0, nt, b->grid, nullptr, nullptr, 0, 0, b->F));
     return launch_reduce(b, kEval, d_poses, 0, (int32_t)b->F, d_e, nullptr, nullptr, nullptr, nullptr);
 }
 
@@ -590,7 +594,7 @@ vg_status linearize_host(vg_batch* b) {
                                   hipMemcpyHostToDevice, st));
             const int32_t t0 = b->h_tile_first[f], t1 = b->h_tile_first[f + 1];
             const int grid = std::max(1, std::min(t1 - t0, b->grid));
-            VG_TRY(launch_tiles(b, kLin, b->d_poses, t0, t1, grid, nullptr, nullptr, 0));
+            VG_TRY(launch_tiles(b, kLin, b->d_poses, t0, t1, grid, nullptr, nullptr, 0, f, f + 1));
             VG_TRY(launch_reduce(b, kLin, b->d_poses, (int32_t)f, (int32_t)f + 1, b->d_out, b->d_inliers, nullptr,
                                  nullptr, nullptr));
             VG_HIP(hipMemcpyAsync(b->h_out + kOutRow * f, b->d_out + kOutRow * f, sizeof(double) * kOutRow,
@@ -623,6 +627,7 @@ void free_batch(vg_batch* b) {
     dfree(b->d_partials);
     dfree(b->d_counter);
     dfree(b->d_poses);
+    dfree(b->d_posef);
     dfree(b->d_out);
     dfree(b->d_inliers);
     dfree(b->d_e);
@@ -711,6 +716,7 @@ extern "C" vg_status vg_create_factor_batch(vg_context* ctx, int64_t F, vg_sourc
         if ((st = dev_alloc(&b->d_fac, F)) != VG_OK) break;
         if ((st = dev_alloc(&b->d_counter, 64)) != VG_OK) break;
         if ((st = dev_alloc(&b->d_poses, 12 * F)) != VG_OK) break;
+        if ((st = dev_alloc(&b->d_posef, 16 * F)) != VG_OK) break;
         if ((st = dev_alloc(&b->d_out, kOutRow * F)) != VG_OK) break;
         if ((st = dev_alloc(&b->d_inliers, (size_t)L * F)) != VG_OK) break;
         if ((st = dev_alloc(&b->d_e, F)) != VG_OK) break;
@@ -832,7 +838,7 @@ extern "C" vg_status vg_backward_async(vg_batch* b, const double* d_poses, const
     if (d_grad_points)
         VG_TRY(launch_zero(b->ctx, d_grad_points, (size_t)b->grad_rows * 3 * (points_dtype ? 8 : 4)));
     const int32_t nt = (int32_t)b->h_tiles.size();
-    VG_TRY(launch_tiles(b, kBwd, d_poses, 0, nt, b->grid, d_grad_e, d_grad_points, points_dtype));
+    VG_TRY(launch_tiles(b, kBwd, d_poses, 0, nt, b->grid, d_grad_e, d_grad_points, points_dtype, 0, b->F));
     return launch_reduce(b, kBwd, d_poses, 0, (int32_t)b->F, nullptr, nullptr, d_grad_e, d_jr, d_grad_xi);
 }
 
@@ -951,7 +957,7 @@ vg_status time_device(vg_batch* b, int reps, float* ms_tiles, float* ms_reduce) 
     vg_status rc = run_linearize_device(b, b->d_poses, b->d_out, b->d_inliers);   // warm-up
     for (int r = 0; r < reps && rc == VG_OK; ++r) {
         (void)hipEventRecord(ev[3 * r], st);
-        rc = launch_tiles(b, kLin, b->d_poses, 0, nt, b->grid, nullptr, nullptr, 0);
+        rc = launch_tiles(b, kLin, b->d_poses, 0, nt, b->grid, nullptr, nullptr, 0, 0, b->F);
         (void)hipEventRecord(ev[3 * r + 1], st);
         if (rc == VG_OK)
             rc = launch_reduce(b, kLin, b->d_poses, 0, (int32_t)b->F, b->d_out, b->d_inliers, nullptr, nullptr,

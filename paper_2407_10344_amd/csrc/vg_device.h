@@ -29,18 +29,57 @@ __host__ __device__ __forceinline__ uint32_t slot_of(uint64_t key, uint32_t log2
     return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - log2cap));
 }
 
-// Open-addressing linear probe.  The table always holds an empty slot (load
-// factor <= 1/2), so the loop ends; the bound is a second guarantee.
+// Open-addressing linear probe.  Slots are read in aligned pairs (one 16-byte
+// load covers slots 2j and 2j+1), walking the same slot order as the insert:
+// h, h+1, h+2, ... until the key or an empty slot.  The table always holds an
+// empty slot (load factor <= 1/4), so the loop ends; the bound is a second
+// guarantee.
 __device__ __forceinline__ int32_t probe(const uint64_t* __restrict__ slots, uint32_t log2cap, uint64_t key) {
     const uint32_t mask = (1u << log2cap) - 1u;
     uint32_t h = slot_of(key, log2cap);
-    for (uint32_t it = 0; it <= mask; ++it) {
-        const uint64_t s = slots[h];
-        if (s == kEmpty) return -1;
-        if ((s >> kIdxBits) == key) return (int32_t)(s & kIdxMask);
-        h = (h + 1u) & mask;
+    for (uint32_t it = 0; it <= mask; it += 2) {
+        const ulonglong2 pr = *reinterpret_cast<const ulonglong2*>(slots + (h & ~1u));
+        if (!(h & 1u)) {
+            if (pr.x == kEmpty) return -1;
+            if ((pr.x >> kIdxBits) == key) return (int32_t)(pr.x & kIdxMask);
+        }
+        if (pr.y == kEmpty) return -1;
+        if ((pr.y >> kIdxBits) == key) return (int32_t)(pr.y & kIdxMask);
+        h = ((h | 1u) + 1u) & mask;
     }
     return -1;
+}
+
+// 1/x without the correctly rounded division sequence: hardware reciprocal
+// refined by Newton steps (two for FP64, each doubling the correct bits).
+__device__ __forceinline__ float recip(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// Position of a point relative to its chunk anchor's coarse voxel corner, in
+// FP32, with an explicit FMA order so every kernel that derives voxel keys
+// from it gets identical bits.
+__device__ __forceinline__ float chunk_pos32(float frac, float r0, float r1, float r2, float dx, float dy,
+                                             float dz) {
+    return frac + fmaf(r2, dz, fmaf(r1, dy, r0 * dx));
+}
+
+// Per-chunk FP64 anchor transform for axis i: ya = (R a + t)_i split into the
+// coarse voxel key (relative to the map origin, clamped far outside the key
+// range) and the remainder inside that voxel.  Shared by every kernel that
+// derives keys from chunk anchors so they agree bit for bit.
+__device__ __forceinline__ void anchor_split(const double* __restrict__ P, const double a[3], int i, double r_top,
+                                             double inv_r_top, int64_t K0_top, double* frac, int32_t* kb) {
+    const double ya = fma(P[3 * i + 2], a[2], fma(P[3 * i + 1], a[1], P[3 * i] * a[0])) + P[9 + i];
+    const double k = floor(ya * inv_r_top);
+    *frac = ya - k * r_top;
+    *kb = (int32_t)fmin(fmax(k - (double)K0_top, -1048576.0), 1048576.0);
 }
 
 // Inverse of a symmetric 3x3 matrix m = [a b c; b d e; c e f] via its adjugate.
@@ -55,7 +94,7 @@ __device__ __forceinline__ void sym3_inverse(const T m[6], T w[6]) {
     const T E = b * c - a * e;
     const T Fv = a * d - b * b;
     const T det = a * A + b * B + c * C;
-    const T s = T(1) / det;
+    const T s = recip(det);
     w[0] = A * s;
     w[1] = B * s;
     w[2] = C * s;

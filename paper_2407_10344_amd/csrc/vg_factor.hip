@@ -25,7 +25,7 @@
 //        quantity (transformed position inside the coarse voxel, residual to a
 //        voxel mean stored relative to its voxel centre, lever arm) is small and
 //        FP32 keeps ~1e-7 m absolute accuracy anywhere in the map.  Lanes sum in
-//        FP32 with Kahan compensation, everything above a lane sums in FP64.
+//        FP32 (optionally Kahan-compensated), everything above a lane in FP64.
 //  kN32: absolute FP32 coordinates and FP32 sums everywhere.
 //  kF64: absolute FP64 coordinates and arithmetic.
 #include <type_traits>
@@ -128,45 +128,127 @@ __device__ __forceinline__ void add_lin_terms(A& acc, const T d[3], const T w[6]
     acc.add(27, -u[2]);
 }
 
+// Per-tile chunk data in LDS.  At 4 waves per SIMD a CU holds at most 16
+// waves, so even one-wave workgroups need at most 16 x 9 KB of the 160 KB.
 struct TileShared {
-    double frac[kMaxTileChunks][3];  // anchor position inside its coarse voxel (kC32)
-    int32_t kb[kMaxTileChunks][3];   // coarse relative key of the anchor (kC32)
-    float za[kMaxTileChunks][3];     // R (anchor - o_s) (kC32)
-    float vc[kMaxTileChunks][3];     // anchor - T^-1 c (kC32, surface validation)
+    double frac[kMaxTileChunks * 3];   // anchor position inside its coarse voxel, FP64 (kC32)
+    float frac32[kMaxTileChunks * 3];  // the same rounded to FP32 (voxel keys)
+    int32_t kb[kMaxTileChunks * 3];    // coarse relative key of the anchor
+    float za[kMaxTileChunks * 3];      // R (anchor - o_s)
+    float vc[kMaxTileChunks * 3];      // anchor - T^-1 c (surface validation)
 };
 
-template <int MODE, int PREC, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_tiles(const FactorDesc* __restrict__ fac, const Tile* __restrict__ tiles,
-                                                 int32_t t_begin, int32_t t_end, const double* __restrict__ poses,
-                                                 double* __restrict__ partials, uint32_t* __restrict__ counter,
-                                                 int32_t validate, const double* __restrict__ grad_e,
-                                                 void* __restrict__ grad_points, int32_t points_dtype) {
+// Raw per-point inputs of one precision mode, loaded one chunk ahead.
+template <int PREC>
+struct RawPoint {
+    float x[3];   // kC32: offset from the chunk anchor; kN32: absolute position
+    float cv[6];
+};
+template <>
+struct RawPoint<kF64> {
+    double x[3];
+    double cv[6];
+};
+
+template <int PREC>
+__device__ __forceinline__ void load_point(const FactorDesc* __restrict__ Fp, int64_t i, int64_t n_pad,
+                                           RawPoint<PREC>& p) {
+    if constexpr (PREC == kC32) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) p.x[a] = Fp->dxyz[a * n_pad + i];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) p.cv[k] = Fp->cov[k * n_pad + i];
+    } else if constexpr (PREC == kN32) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) p.x[a] = Fp->axyz[a * n_pad + i];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) p.cv[k] = Fp->cov[k * n_pad + i];
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) p.x[a] = Fp->xyz64[a * n_pad + i];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) p.cv[k] = Fp->cov64[k * n_pad + i];
+    }
+}
+
+// Register budget: 4 waves per SIMD (<= 128 VGPRs) for the FP32 modes; the
+// FP64 mode needs more and runs at what its register count allows.
+template <int PREC, bool KH>
+constexpr int waves_per_eu() { return (PREC == kF64 || KH) ? 1 : 4; }
+
+// Pose staging: FP32 copies of every factor's R and t (16 floats per factor),
+// read by the tile kernel through uniform (scalar) loads.
+__global__ void k_stage_poses(int64_t F, const double* __restrict__ poses, float* __restrict__ posef) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= F * 16) return;
+    const int64_t f = i / 16, k = i % 16;
+    posef[i] = (k < 12) ? (float)poses[12 * f + k] : 0.0f;
+}
+
+template <int MODE, int PREC, int BLOCK, bool KH>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per_eu<PREC, KH>()))) void k_tiles(
+    const FactorDesc* __restrict__ fac, const Tile* __restrict__ tiles, int32_t t_begin, int32_t t_end,
+    const double* __restrict__ poses, const float* __restrict__ posef, double* __restrict__ partials,
+    uint32_t* __restrict__ counter, int32_t validate, const double* __restrict__ grad_e,
+    void* __restrict__ grad_points, int32_t points_dtype) {
     using T = typename PT<PREC>::T;
     constexpr int NW = BLOCK / 64;
-    constexpr bool KAHAN = (PREC == kC32);
+    constexpr bool KAHAN = KH && (PREC == kC32);
     constexpr int NT = (MODE == kLin) ? kTerms : (MODE == kEval ? 1 : 6);
     __shared__ TileShared sh;
     __shared__ double s_red[NW][kRow];
     __shared__ int32_t s_tile;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    // XCD-aware work distribution: the tile range is cut into kParts contiguous
+    // partitions with one counter each; workgroups are dispatched round-robin
+    // over the XCDs, so workgroup b starts on partition b % kParts and its XCD's
+    // L2 serves a narrow window of factors (which share sources and targets).
+    // A workgroup whose partition is exhausted moves on to the next one.
+    const int32_t span = (t_end - t_begin + kParts - 1) / kParts;
+    int part = (int)(blockIdx.x % kParts);
+    int tried = 0;
 
     for (;;) {
-        if (threadIdx.x == 0) s_tile = t_begin + (int32_t)atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) {
+            int32_t take = -1;
+            while (tried < kParts) {
+                const int32_t lo = t_begin + part * span;
+                const int32_t hi = min(lo + span, t_end);
+                if (lo < hi) {
+                    const uint32_t k = atomicAdd(counter + part, 1u);
+                    if (k < (uint32_t)(hi - lo)) {
+                        take = lo + (int32_t)k;
+                        break;
+                    }
+                }
+                part = (part + 1) % kParts;
+                ++tried;
+            }
+            s_tile = take;
+        }
         __syncthreads();
         const int32_t t = __builtin_amdgcn_readfirstlane(s_tile);
-        if (t >= t_end) break;
+        if (t < 0) break;
         const Tile tile = tiles[t];
         const FactorDesc* __restrict__ Fp = fac + tile.factor;
         const int64_t n = Fp->n, n_pad = Fp->n_pad;
         const int L = Fp->L;
         const double* P = poses + 12 * tile.factor;
-        // pose in registers (uniform)
+        // pose (uniform): FP32 copies from the staged block, FP64 straight from the poses
         T R[9], tt[3];
+        if constexpr (PREC == kF64) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) R[k] = (T)P[k];
+            for (int k = 0; k < 9; ++k) R[k] = P[k];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) tt[k] = (T)P[9 + k];
+            for (int k = 0; k < 3; ++k) tt[k] = P[9 + k];
+        } else {
+            const float* Pf = posef + 16 * (int64_t)tile.factor;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) R[k] = Pf[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) tt[k] = Pf[9 + k];
+        }
         // T^-1 c (source frame) for validation, in FP64
         double cs[3] = {0, 0, 0};
         if (validate) {
@@ -181,20 +263,21 @@ __global__ __launch_bounds__(BLOCK) void k_tiles(const FactorDesc* __restrict__ 
                 const double* a = Fp->anchor + 3 * (int64_t)(tile.chunk0 + c);
                 const double a0 = a[0], a1 = a[1], a2 = a[2];
                 const double o0 = a0 - Fp->src_origin[0], o1 = a1 - Fp->src_origin[1], o2 = a2 - Fp->src_origin[2];
+                const double av[3] = {a0, a1, a2};
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    const double ya = P[3 * i] * a0 + P[3 * i + 1] * a1 + P[3 * i + 2] * a2 + P[9 + i];
-                    const double kb = floor(ya * top.inv_r64);
-                    sh.frac[c][i] = ya - kb * top.r64;
-                    // clamped: anything this far is outside the packable key range anyway
-                    const double rel = fmin(fmax(kb - (double)top.K0[i], -1048576.0), 1048576.0);
-                    sh.kb[c][i] = (int32_t)rel;
-                    sh.za[c][i] = (float)(P[3 * i] * o0 + P[3 * i + 1] * o1 + P[3 * i + 2] * o2);
+                    double fr;
+                    int32_t kb;
+                    anchor_split(P, av, i, top.r64, top.inv_r64, top.K0[i], &fr, &kb);
+                    sh.frac[3 * c + i] = fr;
+                    sh.frac32[3 * c + i] = (float)fr;
+                    sh.kb[3 * c + i] = kb;
+                    sh.za[3 * c + i] = (float)(P[3 * i] * o0 + P[3 * i + 1] * o1 + P[3 * i + 2] * o2);
                 }
                 if (validate) {
-                    sh.vc[c][0] = (float)(a0 - cs[0]);
-                    sh.vc[c][1] = (float)(a1 - cs[1]);
-                    sh.vc[c][2] = (float)(a2 - cs[2]);
+                    sh.vc[3 * c + 0] = (float)(a0 - cs[0]);
+                    sh.vc[3 * c + 1] = (float)(a1 - cs[1]);
+                    sh.vc[3 * c + 2] = (float)(a2 - cs[2]);
                 }
             }
             __syncthreads();
@@ -206,44 +289,53 @@ __global__ __launch_bounds__(BLOCK) void k_tiles(const FactorDesc* __restrict__ 
         double ge = 0.0;
         if constexpr (MODE == kBwd) ge = grad_e[tile.factor];
 
+        // each wave walks chunks wave, wave + NW, ...; the next chunk's point is
+        // loaded before the current one is processed, so its latency overlaps
+        RawPoint<PREC> nxt;
+        if (wave < tile.nchunks) {
+            const int64_t i0 = (int64_t)(tile.chunk0 + wave) * kChunk + lane;
+            if (i0 < n) load_point<PREC>(Fp, i0, n_pad, nxt);
+        }
         for (int c = wave; c < tile.nchunks; c += NW) {
             const int64_t i = (int64_t)(tile.chunk0 + c) * kChunk + lane;
+            const RawPoint<PREC> cur = nxt;
+            if (c + NW < tile.nchunks) {
+                const int64_t in = i + (int64_t)NW * kChunk;
+                if (in < n) load_point<PREC>(Fp, in, n_pad, nxt);
+            }
             if (i >= n) continue;
             // ---- load the point, transform it
             // yl: transformed position (kC32: relative to the anchor's coarse voxel corner)
-            using TY = typename std::conditional<PREC == kC32, double, T>::type;
             T x[3], cv[6], z[3];
-            TY yl[3];
+            T yl[3];          // transformed position (kC32: FP32, relative to the anchor's coarse voxel)
             bool vis = true;
             if constexpr (PREC == kC32) {
-                // The residual d = mu~ - y cancels metre-scale positions down to
-                // centimetres, so the offset from the chunk anchor is rotated and
-                // placed relative to the voxel centre in FP64; d itself and every
-                // term downstream of it are FP32.
-                const float dx = Fp->dxyz[i], dy = Fp->dxyz[n_pad + i], dz = Fp->dxyz[2 * n_pad + i];
+                // Keys come from the FP32 position (its ~5e-7 m error only matters
+                // for points that close to a voxel face, where either voxel is a
+                // valid answer).  The residual d = mu~ - y cancels metre-scale
+                // positions down to centimetres, so for hits the offset from the
+                // anchor is rotated and placed relative to the voxel centre in FP64.
+                const float dx = cur.x[0], dy = cur.x[1], dz = cur.x[2];
 #pragma unroll
-                for (int k = 0; k < 6; ++k) cv[k] = Fp->cov[k * n_pad + i];
-                const double ddx = dx, ddy = dy, ddz = dz;
+                for (int k = 0; k < 6; ++k) cv[k] = cur.cv[k];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const double rd = P[3 * a] * ddx + P[3 * a + 1] * ddy + P[3 * a + 2] * ddz;
-                    yl[a] = sh.frac[c][a] + rd;
-                    z[a] = sh.za[c][a] + (float)rd;
+                    yl[a] = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
+                    z[a] = sh.za[3 * c + a] + fmaf(R[3 * a + 2], dz, fmaf(R[3 * a + 1], dy, R[3 * a] * dx));
                 }
                 x[0] = dx;
                 x[1] = dy;
                 x[2] = dz;
                 if (validate) {
-                    const float s = (sh.vc[c][0] + dx) * Fp->nrm[i] + (sh.vc[c][1] + dy) * Fp->nrm[n_pad + i] +
-                                    (sh.vc[c][2] + dz) * Fp->nrm[2 * n_pad + i];
+                    const float s = (sh.vc[3 * c + 0] + dx) * Fp->nrm[i] + (sh.vc[3 * c + 1] + dy) * Fp->nrm[n_pad + i] +
+                                    (sh.vc[3 * c + 2] + dz) * Fp->nrm[2 * n_pad + i];
                     vis = !(s > 0.0f);
                 }
             } else if constexpr (PREC == kN32) {
-                x[0] = Fp->axyz[i];
-                x[1] = Fp->axyz[n_pad + i];
-                x[2] = Fp->axyz[2 * n_pad + i];
 #pragma unroll
-                for (int k = 0; k < 6; ++k) cv[k] = Fp->cov[k * n_pad + i];
+                for (int a = 0; a < 3; ++a) x[a] = cur.x[a];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) cv[k] = cur.cv[k];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     z[a] = R[3 * a] * x[0] + R[3 * a + 1] * x[1] + R[3 * a + 2] * x[2];
@@ -255,11 +347,10 @@ __global__ __launch_bounds__(BLOCK) void k_tiles(const FactorDesc* __restrict__ 
                     vis = !(s > 0.0f);
                 }
             } else {
-                x[0] = Fp->xyz64[i];
-                x[1] = Fp->xyz64[n_pad + i];
-                x[2] = Fp->xyz64[2 * n_pad + i];
 #pragma unroll
-                for (int k = 0; k < 6; ++k) cv[k] = Fp->cov64[k * n_pad + i];
+                for (int a = 0; a < 3; ++a) x[a] = cur.x[a];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) cv[k] = cur.cv[k];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     z[a] = R[3 * a] * x[0] + R[3 * a + 1] * x[1] + R[3 * a + 2] * x[2];
@@ -300,13 +391,13 @@ __global__ __launch_bounds__(BLOCK) void k_tiles(const FactorDesc* __restrict__ 
                 if (l >= L) break;
                 const LevelDesc& lv = Fp->lv[l];
                 int64_t kq[3];
-                TY pc[3];   // position relative to the voxel centre (kC32), absolute otherwise
+                float jf[3];
+                T pc[3];   // absolute position (kN32, kF64)
                 if constexpr (PREC == kC32) {
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        const double j = floor(yl[a] * lv.inv_r64);
-                        kq[a] = (int64_t)sh.kb[c][a] * lv.scale + (int64_t)j;
-                        pc[a] = yl[a] - (j + 0.5) * lv.r64;
+                        jf[a] = floorf(yl[a] * lv.inv_r);
+                        kq[a] = (int64_t)sh.kb[3 * c + a] * lv.scale + (int64_t)jf[a];
                     }
                 } else if constexpr (PREC == kN32) {
 #pragma unroll
@@ -323,7 +414,11 @@ __global__ __launch_bounds__(BLOCK) void k_tiles(const FactorDesc* __restrict__ 
                         pc[a] = yl[a];
                     }
                 }
-                if (!(key_in_range(kq[0]) && key_in_range(kq[1]) && key_in_range(kq[2]))) continue;
+                // outside the level's key bounding box (also covers keys outside the
+                // packable range): no voxel, no probe
+                if (!(kq[0] >= lv.kmin[0] && kq[0] <= lv.kmax[0] && kq[1] >= lv.kmin[1] && kq[1] <= lv.kmax[1] &&
+                      kq[2] >= lv.kmin[2] && kq[2] <= lv.kmax[2]))
+                    continue;
                 const int32_t v = probe(lv.slots, lv.log2cap, pack_key(kq[0], kq[1], kq[2]));
                 if (v < 0) continue;
                 inl[l] += 1;
@@ -375,8 +470,18 @@ __global__ __launch_bounds__(BLOCK) void k_tiles(const FactorDesc* __restrict__ 
                     sym3_inverse(M, W);
                 }
                 T d[3];
+                if constexpr (PREC == kC32) {
+                    // y relative to the centre of the voxel found above (FP64), then d = mu~ - y
+                    const double ddx = cur.x[0], ddy = cur.x[1], ddz = cur.x[2];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) d[a] = (T)((TY)mv[a] - pc[a]);
+                    for (int a = 0; a < 3; ++a) {
+                        const double y64 = sh.frac[3 * c + a] + (P[3 * a] * ddx + P[3 * a + 1] * ddy + P[3 * a + 2] * ddz);
+                        d[a] = (float)((double)mv[a] - (y64 - ((double)jf[a] + 0.5) * lv.r64));
+                    }
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) d[a] = mv[a] - pc[a];
+                }
                 if constexpr (MODE == kLin) {
                     add_lin_terms(acc, d, W, z);
                 } else if constexpr (MODE == kEval) {
@@ -483,7 +588,7 @@ __global__ __launch_bounds__(64) void k_reduce(const FactorDesc* __restrict__ fa
                                                double* __restrict__ grad_xi) {
     __shared__ double s[kRow];
     const int f = f0 + blockIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < kParts) counter[threadIdx.x] = 0u;
     const int k = threadIdx.x;
     if (k < kRow) {
         const int32_t a = tile_first[f], bnd = tile_first[f + 1];
@@ -596,9 +701,8 @@ __global__ void k_correspondences(const FactorDesc* __restrict__ fac, int64_t fa
         const double dc0 = F.viewpoint[0] - P[9], dc1 = F.viewpoint[1] - P[10], dc2 = F.viewpoint[2] - P[11];
         for (int a = 0; a < 3; ++a) cs[a] = P[a] * dc0 + P[3 + a] * dc1 + P[6 + a] * dc2;
     }
-    using TY = typename std::conditional<PREC == kC32, double, T>::type;
     T R[9], tt[3];
-    TY yl[3];
+    T yl[3];
     for (int k = 0; k < 9; ++k) R[k] = (T)P[k];
     for (int k = 0; k < 3; ++k) tt[k] = (T)P[9 + k];
     bool vis = true;
@@ -609,12 +713,11 @@ __global__ void k_correspondences(const FactorDesc* __restrict__ fac, int64_t fa
         const int64_t c = i / kChunk;
         const double* a = F.anchor + 3 * c;
         const float dx = F.dxyz[i], dy = F.dxyz[n_pad + i], dz = F.dxyz[2 * n_pad + i];
+        const double av[3] = {a[0], a[1], a[2]};
         for (int q = 0; q < 3; ++q) {
-            const double ya = P[3 * q] * a[0] + P[3 * q + 1] * a[1] + P[3 * q + 2] * a[2] + P[9 + q];
-            const double kbd = floor(ya * top.inv_r64);
-            const double frac = ya - kbd * top.r64;
-            kb[q] = (int32_t)fmin(fmax(kbd - (double)top.K0[q], -1048576.0), 1048576.0);
-            yl[q] = frac + (P[3 * q] * (double)dx + P[3 * q + 1] * (double)dy + P[3 * q + 2] * (double)dz);
+            double fr;
+            anchor_split(P, av, q, top.r64, top.inv_r64, top.K0[q], &fr, &kb[q]);
+            yl[q] = chunk_pos32((float)fr, R[3 * q], R[3 * q + 1], R[3 * q + 2], dx, dy, dz);
         }
         if (validate) {
             const float s = ((float)(a[0] - cs[0]) + dx) * F.nrm[i] + ((float)(a[1] - cs[1]) + dy) * F.nrm[n_pad + i] +
@@ -643,7 +746,7 @@ __global__ void k_correspondences(const FactorDesc* __restrict__ fac, int64_t fa
         int64_t kq[3];
         for (int q = 0; q < 3; ++q) {
             if constexpr (PREC == kC32) {
-                kq[q] = (int64_t)kb[q] * lv.scale + (int64_t)floor(yl[q] * lv.inv_r64);
+                kq[q] = (int64_t)kb[q] * lv.scale + (int64_t)floorf(yl[q] * lv.inv_r);
             } else if constexpr (PREC == kN32) {
                 kq[q] = (int64_t)floorf(yl[q] * lv.inv_r) - lv.K0[q];
             } else {
@@ -666,41 +769,45 @@ __global__ void k_fill_zero(uint32_t* p, int64_t n_words) {
 
 // ---------------------------------------------------------------- host launchers
 
-template <int MODE, int PREC>
+template <int MODE, int PREC, bool KH>
 static vg_status launch_tiles_t(vg_batch* b, const double* d_poses, int32_t t0, int32_t t1, int grid,
                                 const double* d_grad_e, void* d_grad_points, int points_dtype) {
     hipStream_t st = b->ctx->stream;
     const int v = b->opt.surface_validation;
+#define VG_LAUNCH(BS)                                                                                         \
+    k_tiles<MODE, PREC, BS, KH><<<grid, BS, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, b->d_posef,        \
+                                                     b->d_partials, b->d_counter, v, d_grad_e, d_grad_points,  \
+                                                     points_dtype)
     switch (b->block) {
-        case 64:
-            k_tiles<MODE, PREC, 64><<<grid, 64, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, b->d_partials,
-                                                        b->d_counter, v, d_grad_e, d_grad_points, points_dtype);
-            break;
-        case 128:
-            k_tiles<MODE, PREC, 128><<<grid, 128, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, b->d_partials,
-                                                          b->d_counter, v, d_grad_e, d_grad_points, points_dtype);
-            break;
-        case 512:
-            k_tiles<MODE, PREC, 512><<<grid, 512, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, b->d_partials,
-                                                          b->d_counter, v, d_grad_e, d_grad_points, points_dtype);
-            break;
-        default:
-            k_tiles<MODE, PREC, 256><<<grid, 256, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, b->d_partials,
-                                                          b->d_counter, v, d_grad_e, d_grad_points, points_dtype);
-            break;
+        case 64: VG_LAUNCH(64); break;
+        case 128: VG_LAUNCH(128); break;
+        case 512: VG_LAUNCH(512); break;
+        default: VG_LAUNCH(256); break;
     }
+#undef VG_LAUNCH
     VG_HIP(hipGetLastError());
     return VG_OK;
 }
 
 vg_status launch_tiles(vg_batch* b, int mode, const double* d_poses, int32_t t0, int32_t t1, int grid,
-                       const double* d_grad_e, void* d_grad_points, int points_dtype) {
+                       const double* d_grad_e, void* d_grad_points, int points_dtype, int64_t f0, int64_t f1) {
     if (grid < 1) grid = 1;
+    if (b->opt.precision != kF64 && f1 > f0) {
+        const int64_t nf = (f1 - f0) * 16;
+        k_stage_poses<<<(int)((nf + 255) / 256), 256, 0, b->ctx->stream>>>(f1 - f0, d_poses + 12 * f0,
+                                                                          b->d_posef + 16 * f0);
+        VG_HIP(hipGetLastError());
+    }
     const int p = b->opt.precision;
-#define VG_DISPATCH(M)                                                                                      \
-    if (p == kC32) return launch_tiles_t<M, kC32>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype); \
-    if (p == kN32) return launch_tiles_t<M, kN32>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype); \
-    return launch_tiles_t<M, kF64>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype);
+    const bool kh = b->opt.lane_kahan != 0;
+#define VG_DISPATCH(M)                                                                                  \
+    if (p == kC32 && kh)                                                                                \
+        return launch_tiles_t<M, kC32, true>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype); \
+    if (p == kC32)                                                                                      \
+        return launch_tiles_t<M, kC32, false>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype); \
+    if (p == kN32)                                                                                      \
+        return launch_tiles_t<M, kN32, false>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype); \
+    return launch_tiles_t<M, kF64, false>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype);
     if (mode == kLin) { VG_DISPATCH(kLin) }
     if (mode == kEval) { VG_DISPATCH(kEval) }
     VG_DISPATCH(kBwd)

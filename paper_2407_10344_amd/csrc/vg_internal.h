@@ -28,6 +28,7 @@ constexpr int kRec32 = 16;              // floats per compensated voxel record (
 constexpr int kRecN = 12;               // floats per absolute-FP32 voxel record
 constexpr int kRec64 = 10;              // doubles per FP64 voxel record
 constexpr int kOutRow = 43;             // e, H (36), b (6)
+constexpr int kParts = 8;               // tile partitions = XCDs of an MI355X
 
 enum Mode { kLin = 0, kEval = 1, kBwd = 2 };
 enum Prec { kN32 = VG_FP32, kC32 = VG_FP32_COMPENSATED, kF64 = VG_FP64 };
@@ -45,6 +46,7 @@ struct LevelDesc {
     float r, inv_r;
     double r64, inv_r64;
     int64_t K0[3];           // absolute key of the map origin at this level
+    int32_t kmin[3], kmax[3];// bounding box of the level's relative keys (empty: min > max)
 };
 
 // One factor: a source cloud (internal Morton order) matched into a target map.
@@ -87,6 +89,7 @@ struct Level {
     double* rec64 = nullptr;
     uint64_t* keys = nullptr;   // V packed relative keys, ascending
     int32_t* counts = nullptr;  // V
+    int32_t kmin[3] = {1, 1, 1}, kmax[3] = {0, 0, 0};   // relative key bounding box
 };
 
 }  // namespace vg
@@ -149,6 +152,7 @@ struct vg_batch {
     double* d_partials = nullptr;
     uint32_t* d_counter = nullptr;
     double* d_poses = nullptr;
+    float* d_posef = nullptr;       // F x 16 staged FP32 poses
     double* d_out = nullptr;        // F x 43
     int64_t* d_inliers = nullptr;   // F x L
     double* d_e = nullptr;          // F (evaluate)
@@ -190,8 +194,9 @@ vg_status layout_source(vg_context* ctx, vg_source* s, const double* d_xyz, cons
 vg_status set_source_points(vg_context* ctx, vg_source* s, const void* d_xyz, int dtype);
 
 // launch the tile kernel over tiles [t0, t1) and the reduction over factors [f0, f1)
+// f0, f1: the factors those tiles belong to (their poses are staged to FP32 first)
 vg_status launch_tiles(vg_batch* b, int mode, const double* d_poses, int32_t t0, int32_t t1, int grid,
-                       const double* d_grad_e, void* d_grad_points, int points_dtype);
+                       const double* d_grad_e, void* d_grad_points, int points_dtype, int64_t f0, int64_t f1);
 vg_status launch_reduce(vg_batch* b, int mode, const double* d_poses, int32_t f0, int32_t f1, double* d_out,
                         int64_t* d_inliers, const double* d_grad_e, const double* d_jr, double* d_grad_xi);
 vg_status launch_correspondences(vg_batch* b, const double* d_pose, int64_t factor, int64_t* d_keys,

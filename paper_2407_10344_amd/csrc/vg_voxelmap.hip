@@ -8,6 +8,8 @@
 // records in three layouts -> open-addressing insert with 64-bit atomicCAS.
 #include <hipcub/hipcub.hpp>
 
+#include <climits>
+
 #include "vg_device.h"
 
 namespace vg {
@@ -81,6 +83,18 @@ __global__ void k_level_stats(const double* __restrict__ xyz, const double* __re
     rN[11] = 0.f;
     keys_out[v] = key;
     counts_out[v] = cnt;
+}
+
+// Bounding box of the level's relative keys (box[0..2] = min, box[3..5] = max).
+__global__ void k_level_bbox(const uint64_t* __restrict__ ukeys, int64_t V, int32_t* __restrict__ box) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    int64_t q[3];
+    unpack_key(ukeys[v], q);
+    for (int a = 0; a < 3; ++a) {
+        atomicMin(box + a, (int32_t)q[a]);
+        atomicMax(box + 3 + a, (int32_t)q[a]);
+    }
 }
 
 __global__ void k_level_insert(const uint64_t* __restrict__ ukeys, int64_t V, uint64_t* __restrict__ slots,
@@ -171,9 +185,10 @@ vg_status build_level(vg_context* ctx, const double* d_xyz, const double* d_cov,
                                                   out->keys, out->counts);
         VG_HIP(hipGetLastError());
     }
-    // capacity: power of two >= 2 V, at least 64 slots
+    // capacity: power of two >= 4 V (load factor <= 1/4, so most misses end at
+    // the first slot), at least 64 slots
     uint32_t lg = 6;
-    while ((1ull << lg) < 2ull * (uint64_t)out->V) ++lg;
+    while ((1ull << lg) < 4ull * (uint64_t)out->V) ++lg;
     out->log2cap = lg;
     const int64_t cap = 1ll << lg;
     VG_HIP(hipMalloc(&out->slots, sizeof(uint64_t) * (size_t)cap));
@@ -182,6 +197,16 @@ vg_status build_level(vg_context* ctx, const double* d_xyz, const double* d_cov,
     if (out->V > 0) {
         k_level_insert<<<grid_of(out->V), 256, 0, st>>>(out->keys, out->V, out->slots, lg);
         VG_HIP(hipGetLastError());
+        int32_t h_box[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
+        VG_HIP(hipMemcpyAsync(d_flag, h_box, sizeof(h_box), hipMemcpyHostToDevice, st));
+        k_level_bbox<<<grid_of(out->V), 256, 0, st>>>(out->keys, out->V, d_flag);
+        VG_HIP(hipGetLastError());
+        VG_HIP(hipMemcpyAsync(h_box, d_flag, sizeof(h_box), hipMemcpyDeviceToHost, st));
+        VG_HIP(hipStreamSynchronize(st));
+        for (int a = 0; a < 3; ++a) {
+            out->kmin[a] = h_box[a];
+            out->kmax[a] = h_box[3 + a];
+        }
     }
     VG_HIP(hipStreamSynchronize(st));
     return VG_OK;

@@ -159,7 +159,8 @@ class FactorBatch:
     """F factors linearized together (one upload, one download per call)."""
 
     def __init__(self, ctx: Context, sources, maps, viewpoints=None, precision="fp32c", validation=False,
-                 use_graph=True, plain=False, block=0, tile=0, blocks_per_cu=0, tune_cache=None):
+                 use_graph=True, plain=False, block=0, tile=0, blocks_per_cu=0, lane_kahan=False,
+                 tune_cache=None):
         lib = load()
         self.ctx = ctx
         self.sources = list(sources)
@@ -177,6 +178,7 @@ class FactorBatch:
         o.block_threads = int(block)
         o.tile_points = int(tile)
         o.blocks_per_cu = int(blocks_per_cu)
+        o.lane_kahan = int(bool(lane_kahan))
         o.tune_cache = tune_cache.encode() if tune_cache else None
         srcs = (C.c_void_p * F)(*[s.handle.value for s in self.sources])
         tgts = (C.c_void_p * F)(*[m.handle.value for m in self.maps])

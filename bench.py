@@ -177,13 +177,13 @@ def main():
         for _ in range(args.profile_steps):
             batch.linearize(poses)
         torch.cuda.synchronize()
-        # a plain device copy of known size, to scale the memory counters
+        # kernels of known traffic, to scale the memory counters: a fill that
+        # writes COPY_BYTES and a reduction that reads them
         src_t = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
-        dst_t = torch.empty_like(src_t)
-        for _ in range(2):
-            dst_t.copy_(src_t)
+        total = src_t.sum()
         torch.cuda.synchronize()
-        log("profile run done: %d linearize steps, 2 copies of %d bytes" % (args.profile_steps, COPY_BYTES))
+        log("profile run done: %d linearize steps; calibration: fill (write) and sum (read) of %d bytes, %s"
+            % (args.profile_steps, COPY_BYTES, float(total)))
         return
 
     for _ in range(args.warmup):

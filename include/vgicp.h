@@ -26,7 +26,7 @@
  *     two, and every resolution is itself a power of two (so y / r is exact).
  *   - Voxel keys are limited to |q - q_origin| < 8192 per axis around the map
  *     origin (the first point snapped to the coarsest voxel), and a level holds
- *     fewer than 4,194,303 voxels.
+ *     fewer than 268,435,454 voxels.
  *
  * Error behaviour: every call returns a vg_status (0 = VG_OK).  No exception
  * crosses the ABI.  On failure vg_last_error() returns a message that stays
@@ -118,7 +118,8 @@ int32_t vg_version(void);
  * 1..4), VG_ERR_KEY_RANGE, VG_ERR_CAPACITY, VG_ERR_OOM, VG_ERR_HIP. */
 vg_status vg_build_voxelmap(vg_context* ctx, const double* xyz, const double* cov, int64_t n,
                             const double* resolutions, int32_t L, vg_voxelmap** out);
-/* Number of voxels of a level and the hash-table capacity (slots). */
+/* Number of voxels of a level and the capacity (entries) of its block table:
+ * voxels are grouped in 4x4x4 blocks, one hash entry per occupied block. */
 vg_status vg_voxelmap_info(const vg_voxelmap* map, int32_t level, int64_t* n_voxels,
                            int64_t* capacity);
 /* Copy a level to the host in canonical order (ascending lexicographic key).

@@ -223,19 +223,10 @@ extern "C" vg_status vg_build_voxelmap(vg_context* ctx, const double* xyz, const
     const double rmax = resolutions[L - 1];
     for (int a = 0; a < 3; ++a) m->origin[a] = (n > 0) ? rmax * std::nearbyint(xyz[a] / rmax) : 0.0;
     double *d_xyz = nullptr, *d_cov = nullptr;
-    uint64_t* d_keys = nullptr;
-    int32_t* d_idx = nullptr;
-    int32_t* d_flag = nullptr;
-    void* d_tmp = nullptr;
-    const size_t tmp_bytes = build_level_scratch_bytes(n);
     vg_status st = VG_OK;
     do {
         if ((st = dev_alloc(&d_xyz, 3 * n)) != VG_OK) break;
         if ((st = dev_alloc(&d_cov, 6 * n)) != VG_OK) break;
-        if ((st = dev_alloc(&d_keys, 3 * n + 64)) != VG_OK) break;
-        if ((st = dev_alloc(&d_idx, 4 * n + 64)) != VG_OK) break;
-        if ((st = dev_alloc(&d_flag, 64)) != VG_OK) break;
-        if ((st = dev_alloc((char**)&d_tmp, tmp_bytes)) != VG_OK) break;
         hipError_t e = hipSuccess;
         if (n > 0) {
             e = hipMemcpyAsync(d_xyz, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, ctx->stream);
@@ -247,15 +238,10 @@ extern "C" vg_status vg_build_voxelmap(vg_context* ctx, const double* xyz, const
             break;
         }
         for (int l = 0; l < L && st == VG_OK; ++l)
-            st = build_level(ctx, d_xyz, d_cov, n, resolutions[l], m->origin, &m->lv[l], d_keys, d_idx, d_tmp,
-                             tmp_bytes, d_flag);
+            st = build_level(ctx, d_xyz, d_cov, n, resolutions[l], m->origin, &m->lv[l]);
     } while (0);
     dfree(d_xyz);
     dfree(d_cov);
-    dfree(d_keys);
-    dfree(d_idx);
-    dfree(d_flag);
-    dfree(d_tmp);
     if (st != VG_OK) {
         for (int l = 0; l < kMaxLevels; ++l) free_level(&m->lv[l]);
         delete m;

@@ -6,6 +6,19 @@
 
 namespace vg {
 
+// Global-address-space view of a device pointer read from a descriptor in
+// memory: loads through it compile to global_load (not flat_load, which also
+// waits on the LDS counter).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gbl(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+
+// Native vector types for 16-byte loads through global pointers.
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
 // Relative voxel key (|k| < 8192 per axis) packed into 42 bits; x is the most
 // significant field, so ascending packed keys are ascending lexicographic keys.
 __host__ __device__ __forceinline__ bool key_in_range(int64_t k) {
@@ -29,23 +42,38 @@ __host__ __device__ __forceinline__ uint32_t slot_of(uint64_t key, uint32_t log2
     return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - log2cap));
 }
 
-// Open-addressing linear probe.  Slots are read in aligned pairs (one 16-byte
-// load covers slots 2j and 2j+1), walking the same slot order as the insert:
-// h, h+1, h+2, ... until the key or an empty slot.  The table always holds an
-// empty slot (load factor <= 1/4), so the loop ends; the bound is a second
-// guarantee.
-__device__ __forceinline__ int32_t probe(const uint64_t* __restrict__ slots, uint32_t log2cap, uint64_t key) {
+// Sparse-block voxel lookup.  Voxels are grouped in 4 x 4 x 4 blocks; a hash
+// table (open addressing, linear probing, load factor <= 1/4) maps each
+// occupied block to one 16-byte entry: (block key << 28 | index of the block's
+// first record) and a 64-bit occupancy mask.  Records are stored block by
+// block, in Morton order inside a block, so a voxel's record index is
+// first + popcount(mask below its bit).  Neighbouring points share block
+// entries and read neighbouring records.
+__host__ __device__ __forceinline__ uint32_t block_local(uint64_t ux, uint64_t uy, uint64_t uz) {
+    return (uint32_t)((ux & 1) | ((uy & 1) << 1) | ((uz & 1) << 2) | (((ux >> 1) & 1) << 3) |
+                      (((uy >> 1) & 1) << 4) | (((uz >> 1) & 1) << 5));
+}
+
+__host__ __device__ __forceinline__ uint64_t block_key(uint64_t ux, uint64_t uy, uint64_t uz) {
+    return ((ux >> kBlockShift) << (2 * kBlockBits)) | ((uy >> kBlockShift) << kBlockBits) | (uz >> kBlockShift);
+}
+
+// Record index of relative key (kx, ky, kz) (each in [-8192, 8191]), or -1.
+__device__ __forceinline__ int32_t lookup(const uint64_t* __restrict__ slots, uint32_t log2cap, int64_t kx,
+                                          int64_t ky, int64_t kz) {
+    const uint64_t ux = (uint64_t)(kx + kKeyBias), uy = (uint64_t)(ky + kKeyBias), uz = (uint64_t)(kz + kKeyBias);
+    const uint64_t bk = block_key(ux, uy, uz);
+    const uint64_t bit = 1ull << block_local(ux, uy, uz);
     const uint32_t mask = (1u << log2cap) - 1u;
-    uint32_t h = slot_of(key, log2cap);
-    for (uint32_t it = 0; it <= mask; it += 2) {
-        const ulonglong2 pr = *reinterpret_cast<const ulonglong2*>(slots + (h & ~1u));
-        if (!(h & 1u)) {
-            if (pr.x == kEmpty) return -1;
-            if ((pr.x >> kIdxBits) == key) return (int32_t)(pr.x & kIdxMask);
+    uint32_t h = slot_of(bk, log2cap);
+    for (uint32_t it = 0; it <= mask; ++it) {
+        const u64x2 e = *gbl(reinterpret_cast<const u64x2*>(slots + 2 * (uint64_t)h));
+        if (e.x == kEmpty) return -1;
+        if ((e.x >> kBaseBits) == bk) {
+            if (!(e.y & bit)) return -1;
+            return (int32_t)(e.x & kBaseMask) + __popcll(e.y & (bit - 1));
         }
-        if (pr.y == kEmpty) return -1;
-        if ((pr.y >> kIdxBits) == key) return (int32_t)(pr.y & kIdxMask);
-        h = ((h | 1u) + 1u) & mask;
+        h = (h + 1u) & mask;
     }
     return -1;
 }

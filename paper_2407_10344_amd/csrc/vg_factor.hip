@@ -154,20 +154,26 @@ template <int PREC>
 __device__ __forceinline__ void load_point(const FactorDesc* __restrict__ Fp, int64_t i, int64_t n_pad,
                                            RawPoint<PREC>& p) {
     if constexpr (PREC == kC32) {
+        const auto X = gbl(Fp->dxyz);
+        const auto Cv = gbl(Fp->cov);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) p.x[a] = Fp->dxyz[a * n_pad + i];
+        for (int a = 0; a < 3; ++a) p.x[a] = X[a * n_pad + i];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) p.cv[k] = Fp->cov[k * n_pad + i];
+        for (int k = 0; k < 6; ++k) p.cv[k] = Cv[k * n_pad + i];
     } else if constexpr (PREC == kN32) {
+        const auto X = gbl(Fp->axyz);
+        const auto Cv = gbl(Fp->cov);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) p.x[a] = Fp->axyz[a * n_pad + i];
+        for (int a = 0; a < 3; ++a) p.x[a] = X[a * n_pad + i];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) p.cv[k] = Fp->cov[k * n_pad + i];
+        for (int k = 0; k < 6; ++k) p.cv[k] = Cv[k * n_pad + i];
     } else {
+        const auto X = gbl(Fp->xyz64);
+        const auto Cv = gbl(Fp->cov64);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) p.x[a] = Fp->xyz64[a * n_pad + i];
+        for (int a = 0; a < 3; ++a) p.x[a] = X[a * n_pad + i];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) p.cv[k] = Fp->cov64[k * n_pad + i];
+        for (int k = 0; k < 6; ++k) p.cv[k] = Cv[k * n_pad + i];
     }
 }
 
@@ -260,7 +266,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
         if constexpr (PREC == kC32) {
             const LevelDesc& top = Fp->lv[L - 1];
             for (int c = threadIdx.x; c < tile.nchunks; c += BLOCK) {
-                const double* a = Fp->anchor + 3 * (int64_t)(tile.chunk0 + c);
+                const auto a = gbl(Fp->anchor + 3 * (int64_t)(tile.chunk0 + c));
                 const double a0 = a[0], a1 = a[1], a2 = a[2];
                 const double o0 = a0 - Fp->src_origin[0], o1 = a1 - Fp->src_origin[1], o2 = a2 - Fp->src_origin[2];
                 const double av[3] = {a0, a1, a2};
@@ -419,7 +425,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 if (!(kq[0] >= lv.kmin[0] && kq[0] <= lv.kmax[0] && kq[1] >= lv.kmin[1] && kq[1] <= lv.kmax[1] &&
                       kq[2] >= lv.kmin[2] && kq[2] <= lv.kmax[2]))
                     continue;
-                const int32_t v = probe(lv.slots, lv.log2cap, pack_key(kq[0], kq[1], kq[2]));
+                const int32_t v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
                 if (v < 0) continue;
                 inl[l] += 1;
                 if (!haveS) {
@@ -438,8 +444,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 T mv[3];
                 T W[6];
                 if constexpr (PREC == kC32) {
-                    const float4* r4 = reinterpret_cast<const float4*>(lv.rec32 + (int64_t)v * kRec32);
-                    const float4 q0 = r4[0], q1 = r4[1], q2 = r4[2], q3 = r4[3];
+                    const auto r4 = gbl(reinterpret_cast<const f32x4*>(lv.rec32 + (int64_t)v * kRec32));
+                    const f32x4 q0 = r4[0], q1 = r4[1], q2 = r4[2], q3 = r4[3];
                     mv[0] = q0.x; mv[1] = q0.y; mv[2] = q0.z;
                     double M[6], W64[6];
                     M[0] = ((double)q0.w + (double)q2.y) + S[0];
@@ -454,13 +460,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 } else {
                     T cvv[6];
                     if constexpr (PREC == kN32) {
-                        const float4* r4 = reinterpret_cast<const float4*>(lv.recN + (int64_t)v * kRecN);
-                        const float4 q0 = r4[0], q1 = r4[1], q2 = r4[2];
+                        const auto r4 = gbl(reinterpret_cast<const f32x4*>(lv.recN + (int64_t)v * kRecN));
+                        const f32x4 q0 = r4[0], q1 = r4[1], q2 = r4[2];
                         mv[0] = q0.x; mv[1] = q0.y; mv[2] = q0.z;
                         cvv[0] = q0.w; cvv[1] = q1.x; cvv[2] = q1.y; cvv[3] = q1.z; cvv[4] = q1.w; cvv[5] = q2.x;
                     } else {
-                        const double2* r2 = reinterpret_cast<const double2*>(lv.rec64 + (int64_t)v * kRec64);
-                        const double2 q0 = r2[0], q1 = r2[1], q2 = r2[2], q3 = r2[3], q4 = r2[4];
+                        const auto r2 = gbl(reinterpret_cast<const f64x2*>(lv.rec64 + (int64_t)v * kRec64));
+                        const f64x2 q0 = r2[0], q1 = r2[1], q2 = r2[2], q3 = r2[3], q4 = r2[4];
                         mv[0] = q0.x; mv[1] = q0.y; mv[2] = q1.x;
                         cvv[0] = q1.y; cvv[1] = q2.x; cvv[2] = q2.y; cvv[3] = q3.x; cvv[4] = q3.y; cvv[5] = q4.x;
                     }
@@ -757,7 +763,7 @@ __global__ void k_correspondences(const FactorDesc* __restrict__ fac, int64_t fa
         int32_t fnd;
         if (!vis) fnd = -1;
         else if (!(key_in_range(kq[0]) && key_in_range(kq[1]) && key_in_range(kq[2]))) fnd = 0;
-        else fnd = probe(lv.slots, lv.log2cap, pack_key(kq[0], kq[1], kq[2])) >= 0 ? 1 : 0;
+        else fnd = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]) >= 0 ? 1 : 0;
         found[row * L + l] = fnd;
     }
 }

@@ -17,10 +17,12 @@ constexpr int kMaxLevels = 4;
 constexpr int kChunk = 64;              // points per anchor chunk == one wavefront
 constexpr int kKeyBits = 14;            // bits per axis of a packed relative voxel key
 constexpr int kKeyBias = 1 << (kKeyBits - 1);   // relative keys live in [-8192, 8191]
-constexpr int kIdxBits = 22;            // voxel index bits of a hash slot
-constexpr uint64_t kIdxMask = (1ull << kIdxBits) - 1;
-constexpr int64_t kMaxVoxels = (int64_t)kIdxMask - 1;   // idx 0x3FFFFF never valid
-constexpr uint64_t kEmpty = ~0ull;      // empty hash slot (never a valid key|idx)
+constexpr int kBlockShift = 2;          // voxel blocks of 4 x 4 x 4
+constexpr int kBlockBits = kKeyBits - kBlockShift;   // 12 bits per axis of a block key
+constexpr int kBaseBits = 28;           // first-record index bits of a block entry
+constexpr uint64_t kBaseMask = (1ull << kBaseBits) - 1;
+constexpr int64_t kMaxVoxels = (int64_t)kBaseMask - 1;  // so a valid entry word is never all ones
+constexpr uint64_t kEmpty = ~0ull;      // empty block-table entry
 constexpr int kRow = 32;                // partial row: 28 terms + 4 inlier counts
 constexpr int kTerms = 28;              // e, 21 upper-triangular H, 6 b
 constexpr int kMaxTileChunks = 128;     // at most 8192 points per tile
@@ -37,7 +39,8 @@ enum Prec { kN32 = VG_FP32, kC32 = VG_FP32_COMPENSATED, kF64 = VG_FP64 };
 
 // One level of a target voxel map as the kernels see it.
 struct LevelDesc {
-    const uint64_t* slots;   // 2^log2cap slots: (packed relative key << 22) | voxel index
+    const uint64_t* slots;   // 2^log2cap block entries of two words:
+                             //   [(36-bit block key << 28) | first record, 64-bit occupancy]
     const float* rec32;      // V x 16: mean - voxel centre (3), cov hi (6), cov lo (6), count
     const float* recN;       // V x 12: FP32 absolute mean (3), cov (6), pad
     const double* rec64;     // V x 10: absolute mean (3), cov (6), pad
@@ -82,13 +85,15 @@ struct Level {
     double r = 0;
     int64_t K0[3] = {0, 0, 0};
     int64_t V = 0;
-    uint32_t log2cap = 0;
-    uint64_t* slots = nullptr;
+    uint32_t log2cap = 0;      // block-table entries = 2^log2cap
+    int64_t n_blocks = 0;
+    uint64_t* slots = nullptr; // 2 words per entry
     float* rec32 = nullptr;
     float* recN = nullptr;
     double* rec64 = nullptr;
-    uint64_t* keys = nullptr;   // V packed relative keys, ascending
-    int32_t* counts = nullptr;  // V
+    uint64_t* keys = nullptr;   // V packed relative keys, ascending (canonical order)
+    int32_t* counts = nullptr;  // V, canonical order
+    int32_t* lex2rec = nullptr; // V: canonical index -> record index (records are block ordered)
     int32_t kmin[3] = {1, 1, 1}, kmax[3] = {0, 0, 0};   // relative key bounding box
 };
 
@@ -182,9 +187,7 @@ vg_status hip_fail(hipError_t e, const char* what);
 // ---------------------------------------------------------------- launchers (device code)
 
 vg_status build_level(vg_context* ctx, const double* d_xyz, const double* d_cov, int64_t n, double r,
-                      const double origin[3], Level* out, uint64_t* d_scratch_keys, int32_t* d_scratch_idx,
-                      void* d_sort_tmp, size_t sort_tmp_bytes, int32_t* d_flag);
-size_t build_level_scratch_bytes(int64_t n);
+                      const double origin[3], Level* out);
 vg_status export_level(vg_context* ctx, const Level& lv, int64_t* keys, double* means, double* covs,
                        int64_t* counts);
 void free_level(Level* lv);

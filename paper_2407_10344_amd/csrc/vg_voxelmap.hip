@@ -9,6 +9,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <climits>
+#include <vector>
 
 #include "vg_device.h"
 
@@ -31,12 +32,15 @@ __global__ void k_level_keys(const double* __restrict__ xyz, int64_t n, double r
     idx[i] = (int32_t)i;
 }
 
+// Per-voxel statistics of voxel v (canonical = ascending-key order): FP64 sums
+// of its points in ascending point order, then the average; records are
+// written at position pos[v] (block order).
 __global__ void k_level_stats(const double* __restrict__ xyz, const double* __restrict__ cov,
                               const uint64_t* __restrict__ ukeys, const int32_t* __restrict__ counts,
-                              const int32_t* __restrict__ offsets, const int32_t* __restrict__ sorted_idx, int64_t V,
-                              double r, int64_t K0x, int64_t K0y, int64_t K0z, float* __restrict__ rec32,
-                              float* __restrict__ recN, double* __restrict__ rec64, uint64_t* __restrict__ keys_out,
-                              int32_t* __restrict__ counts_out) {
+                              const int32_t* __restrict__ offsets, const int32_t* __restrict__ sorted_idx,
+                              const int32_t* __restrict__ pos, int64_t V, double r, int64_t K0x, int64_t K0y,
+                              int64_t K0z, float* __restrict__ rec32, float* __restrict__ recN,
+                              double* __restrict__ rec64) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
     const int32_t off = offsets[v], cnt = counts[v];
@@ -52,15 +56,15 @@ __global__ void k_level_stats(const double* __restrict__ xyz, const double* __re
     double m[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) m[k] = s[k] / (double)cnt;
-    const uint64_t key = ukeys[v];
     int64_t q[3];
-    unpack_key(key, q);
+    unpack_key(ukeys[v], q);
     q[0] += K0x;
     q[1] += K0y;
     q[2] += K0z;
-    double* r64 = rec64 + kRec64 * v;
-    float* r32 = rec32 + kRec32 * v;
-    float* rN = recN + kRecN * v;
+    const int64_t w = pos[v];
+    double* r64 = rec64 + kRec64 * w;
+    float* r32 = rec32 + kRec32 * w;
+    float* rN = recN + kRecN * w;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double centre = (double)q[a] * r + 0.5 * r;
@@ -81,8 +85,52 @@ __global__ void k_level_stats(const double* __restrict__ xyz, const double* __re
     rN[9] = 0.f;
     rN[10] = 0.f;
     rN[11] = 0.f;
-    keys_out[v] = key;
-    counts_out[v] = cnt;
+}
+
+// Block-order sort key of voxel v: (block key << 6) | Morton index inside the block.
+__global__ void k_block_codes(const uint64_t* __restrict__ ukeys, int64_t V, uint64_t* __restrict__ codes,
+                              int32_t* __restrict__ idx) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    int64_t q[3];
+    unpack_key(ukeys[v], q);
+    const uint64_t ux = (uint64_t)(q[0] + kKeyBias), uy = (uint64_t)(q[1] + kKeyBias), uz = (uint64_t)(q[2] + kKeyBias);
+    codes[v] = (block_key(ux, uy, uz) << 6) | block_local(ux, uy, uz);
+    idx[v] = (int32_t)v;
+}
+
+// pos[canonical index] = record position, and the block key of every record.
+__global__ void k_block_scatter(const uint64_t* __restrict__ codes_sorted, const int32_t* __restrict__ idx_sorted,
+                                int64_t V, int32_t* __restrict__ pos, uint64_t* __restrict__ bkeys) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= V) return;
+    pos[idx_sorted[m]] = (int32_t)m;
+    bkeys[m] = codes_sorted[m] >> 6;
+}
+
+// One thread per occupied block: occupancy mask of its records, then insertion
+// of (block key | first record, mask) into the block table.
+__global__ void k_block_insert(const uint64_t* __restrict__ ublocks, const int32_t* __restrict__ bcounts,
+                               const int32_t* __restrict__ boffsets, const uint64_t* __restrict__ codes_sorted,
+                               int64_t NB, uint64_t* __restrict__ slots, uint32_t log2cap) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= NB) return;
+    const int32_t base = boffsets[b], cnt = bcounts[b];
+    uint64_t occ = 0;
+    for (int32_t m = base; m < base + cnt; ++m) occ |= 1ull << (codes_sorted[m] & 63);
+    const uint64_t key = ublocks[b];
+    const uint64_t word = (key << kBaseBits) | (uint64_t)base;
+    const uint32_t mask = (1u << log2cap) - 1u;
+    uint32_t h = slot_of(key, log2cap);
+    for (uint32_t it = 0; it <= mask; ++it) {
+        const unsigned long long prev = atomicCAS((unsigned long long*)(slots + 2 * (uint64_t)h),
+                                                  (unsigned long long)kEmpty, (unsigned long long)word);
+        if (prev == (unsigned long long)kEmpty) {
+            slots[2 * (uint64_t)h + 1] = occ;
+            return;
+        }
+        h = (h + 1u) & mask;
+    }
 }
 
 // Bounding box of the level's relative keys (box[0..2] = min, box[3..5] = max).
@@ -97,22 +145,6 @@ __global__ void k_level_bbox(const uint64_t* __restrict__ ukeys, int64_t V, int3
     }
 }
 
-__global__ void k_level_insert(const uint64_t* __restrict__ ukeys, int64_t V, uint64_t* __restrict__ slots,
-                               uint32_t log2cap) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
-    const uint64_t key = ukeys[v];
-    const uint64_t val = (key << kIdxBits) | (uint64_t)v;
-    const uint32_t mask = (1u << log2cap) - 1u;
-    uint32_t h = slot_of(key, log2cap);
-    for (uint32_t it = 0; it <= mask; ++it) {
-        const unsigned long long prev =
-            atomicCAS((unsigned long long*)(slots + h), (unsigned long long)kEmpty, (unsigned long long)val);
-        if (prev == (unsigned long long)kEmpty) return;
-        h = (h + 1u) & mask;
-    }
-}
-
 __global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -120,93 +152,143 @@ __global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
 
 static int grid_of(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
 
-size_t build_level_scratch_bytes(int64_t n) {
-    size_t a = 0, b = 0, c = 0;
-    const int N = (int)(n > 0 ? n : 1);
-    hipcub::DeviceRadixSort::SortPairs(nullptr, a, (uint64_t*)nullptr, (uint64_t*)nullptr, (int32_t*)nullptr,
-                                       (int32_t*)nullptr, N, 0, 3 * kKeyBits);
-    hipcub::DeviceRunLengthEncode::Encode(nullptr, b, (uint64_t*)nullptr, (uint64_t*)nullptr, (int32_t*)nullptr,
-                                          (int32_t*)nullptr, N);
-    hipcub::DeviceScan::ExclusiveSum(nullptr, c, (int32_t*)nullptr, (int32_t*)nullptr, N);
-    return std::max(a, std::max(b, c)) + 256;
-}
+namespace {
+// Device scratch owned by one build call.
+struct Scratch {
+    std::vector<void*> ptrs;
+    ~Scratch() {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    template <typename T>
+    hipError_t get(T** p, size_t count) {
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, sizeof(T) * (count ? count : 1));
+        if (e == hipSuccess) ptrs.push_back(q);
+        *p = (T*)q;
+        return e;
+    }
+};
+}  // namespace
 
-// Scratch layout (n entries each): keys_in, keys_out (u64), idx_in, idx_out,
-// counts, offsets (i32), unique keys (u64), and `d_sort_tmp` for hipcub.
 vg_status build_level(vg_context* ctx, const double* d_xyz, const double* d_cov, int64_t n, double r,
-                      const double origin[3], Level* out, uint64_t* d_scratch_keys, int32_t* d_scratch_idx,
-                      void* d_sort_tmp, size_t sort_tmp_bytes, int32_t* d_flag) {
+                      const double origin[3], Level* out) {
     hipStream_t st = ctx->stream;
     out->r = r;
     for (int a = 0; a < 3; ++a) out->K0[a] = (int64_t)llround(origin[a] / r);
     out->V = 0;
+    out->n_blocks = 0;
+    Scratch sc;
+    int32_t* d_small = nullptr;   // flag, run counts, bbox
+    VG_HIP(sc.get(&d_small, 64));
     if (n > 0) {
-        uint64_t* keys_in = d_scratch_keys;
-        uint64_t* keys_out = d_scratch_keys + n;
-        uint64_t* ukeys = d_scratch_keys + 2 * n;
-        int32_t* idx_in = d_scratch_idx;
-        int32_t* idx_out = d_scratch_idx + n;
-        int32_t* counts = d_scratch_idx + 2 * n;
-        int32_t* offsets = d_scratch_idx + 3 * n;
-        int32_t* nruns = d_scratch_idx + 4 * n;
-        VG_HIP(hipMemsetAsync(d_flag, 0, sizeof(int32_t), st));
+        uint64_t *keys_in, *keys_out, *ukeys, *codes, *codes_sorted, *bkeys, *ublocks;
+        int32_t *idx_in, *idx_out, *counts, *offsets, *vidx, *vidx_sorted, *pos, *bcounts, *boffsets;
+        VG_HIP(sc.get(&keys_in, n));
+        VG_HIP(sc.get(&keys_out, n));
+        VG_HIP(sc.get(&idx_in, n));
+        VG_HIP(sc.get(&idx_out, n));
+        VG_HIP(sc.get(&counts, n));
+        VG_HIP(sc.get(&offsets, n));
+        size_t tmp_bytes = 0, b2 = 0, b3 = 0;
+        (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys_in, keys_out, idx_in, idx_out, (int)n, 0,
+                                                 3 * kKeyBits);
+        (void)hipcub::DeviceRunLengthEncode::Encode(nullptr, b2, keys_out, keys_in, counts, d_small, (int)n);
+        (void)hipcub::DeviceScan::ExclusiveSum(nullptr, b3, counts, offsets, (int)n);
+        tmp_bytes = std::max(tmp_bytes, std::max(b2, b3)) + 256;
+        void* tmp = nullptr;
+        VG_HIP(sc.get((char**)&tmp, tmp_bytes));
+        // 1. keys of every point, stable sort by key, runs = voxels
+        VG_HIP(hipMemsetAsync(d_small, 0, sizeof(int32_t), st));
         k_level_keys<<<grid_of(n), 256, 0, st>>>(d_xyz, n, r, out->K0[0], out->K0[1], out->K0[2], keys_in, idx_in,
-                                                 d_flag);
+                                                 d_small);
         VG_HIP(hipGetLastError());
         int32_t h_flag = 0;
-        VG_HIP(hipMemcpyAsync(&h_flag, d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        VG_HIP(hipMemcpyAsync(&h_flag, d_small, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         VG_HIP(hipStreamSynchronize(st));
         if (h_flag) {
             set_error("voxel key outside the packable range (|q - q_origin| >= 8192 voxels on an axis)");
             return VG_ERR_KEY_RANGE;
         }
-        size_t tb = sort_tmp_bytes;
-        VG_HIP(hipcub::DeviceRadixSort::SortPairs(d_sort_tmp, tb, keys_in, keys_out, idx_in, idx_out, (int)n, 0,
+        size_t tb = tmp_bytes;
+        VG_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, keys_in, keys_out, idx_in, idx_out, (int)n, 0,
                                                   3 * kKeyBits, st));
-        tb = sort_tmp_bytes;
-        VG_HIP(hipcub::DeviceRunLengthEncode::Encode(d_sort_tmp, tb, keys_out, ukeys, counts, nruns, (int)n, st));
+        VG_HIP(sc.get(&ukeys, n));
+        tb = tmp_bytes;
+        VG_HIP(hipcub::DeviceRunLengthEncode::Encode(tmp, tb, keys_out, ukeys, counts, d_small + 1, (int)n, st));
         int32_t V = 0;
-        VG_HIP(hipMemcpyAsync(&V, nruns, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        VG_HIP(hipMemcpyAsync(&V, d_small + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         VG_HIP(hipStreamSynchronize(st));
         if (V > kMaxVoxels) {
             set_error("too many voxels in one level");
             return VG_ERR_CAPACITY;
         }
-        tb = sort_tmp_bytes;
-        VG_HIP(hipcub::DeviceScan::ExclusiveSum(d_sort_tmp, tb, counts, offsets, V, st));
+        tb = tmp_bytes;
+        VG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, counts, offsets, V, st));
         out->V = V;
+        // 2. block order of the voxels and their record positions
+        VG_HIP(sc.get(&codes, V));
+        VG_HIP(sc.get(&codes_sorted, V));
+        VG_HIP(sc.get(&vidx, V));
+        VG_HIP(sc.get(&vidx_sorted, V));
+        VG_HIP(sc.get(&bkeys, V));
+        VG_HIP(sc.get(&ublocks, V));
+        VG_HIP(sc.get(&bcounts, V));
+        VG_HIP(sc.get(&boffsets, V));
+        VG_HIP(hipMalloc(&out->lex2rec, sizeof(int32_t) * (size_t)V));
+        pos = out->lex2rec;
+        k_block_codes<<<grid_of(V), 256, 0, st>>>(ukeys, V, codes, vidx);
+        VG_HIP(hipGetLastError());
+        tb = tmp_bytes;
+        VG_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, codes, codes_sorted, vidx, vidx_sorted, V, 0,
+                                                  3 * kBlockBits + 6, st));
+        k_block_scatter<<<grid_of(V), 256, 0, st>>>(codes_sorted, vidx_sorted, V, pos, bkeys);
+        VG_HIP(hipGetLastError());
+        tb = tmp_bytes;
+        VG_HIP(hipcub::DeviceRunLengthEncode::Encode(tmp, tb, bkeys, ublocks, bcounts, d_small + 2, V, st));
+        int32_t NB = 0;
+        VG_HIP(hipMemcpyAsync(&NB, d_small + 2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        VG_HIP(hipStreamSynchronize(st));
+        tb = tmp_bytes;
+        VG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, bcounts, boffsets, NB, st));
+        out->n_blocks = NB;
+        // 3. records in block order
         VG_HIP(hipMalloc(&out->rec32, sizeof(float) * kRec32 * (size_t)V));
         VG_HIP(hipMalloc(&out->recN, sizeof(float) * kRecN * (size_t)V));
         VG_HIP(hipMalloc(&out->rec64, sizeof(double) * kRec64 * (size_t)V));
         VG_HIP(hipMalloc(&out->keys, sizeof(uint64_t) * (size_t)V));
         VG_HIP(hipMalloc(&out->counts, sizeof(int32_t) * (size_t)V));
-        k_level_stats<<<grid_of(V), 256, 0, st>>>(d_xyz, d_cov, ukeys, counts, offsets, idx_out, V, r, out->K0[0],
-                                                  out->K0[1], out->K0[2], out->rec32, out->recN, out->rec64,
-                                                  out->keys, out->counts);
+        k_level_stats<<<grid_of(V), 256, 0, st>>>(d_xyz, d_cov, ukeys, counts, offsets, idx_out, pos, V, r,
+                                                  out->K0[0], out->K0[1], out->K0[2], out->rec32, out->recN,
+                                                  out->rec64);
         VG_HIP(hipGetLastError());
-    }
-    // capacity: power of two >= 4 V (load factor <= 1/4, so most misses end at
-    // the first slot), at least 64 slots
-    uint32_t lg = 6;
-    while ((1ull << lg) < 4ull * (uint64_t)out->V) ++lg;
-    out->log2cap = lg;
-    const int64_t cap = 1ll << lg;
-    VG_HIP(hipMalloc(&out->slots, sizeof(uint64_t) * (size_t)cap));
-    k_fill_u64<<<grid_of(cap), 256, 0, st>>>(out->slots, cap, kEmpty);
-    VG_HIP(hipGetLastError());
-    if (out->V > 0) {
-        k_level_insert<<<grid_of(out->V), 256, 0, st>>>(out->keys, out->V, out->slots, lg);
+        VG_HIP(hipMemcpyAsync(out->keys, ukeys, sizeof(uint64_t) * V, hipMemcpyDeviceToDevice, st));
+        VG_HIP(hipMemcpyAsync(out->counts, counts, sizeof(int32_t) * V, hipMemcpyDeviceToDevice, st));
+        // 4. block table: power of two >= 4 x blocks (load factor <= 1/4)
+        uint32_t lg = 6;
+        while ((1ull << lg) < 4ull * (uint64_t)NB) ++lg;
+        out->log2cap = lg;
+        const int64_t cap = 1ll << lg;
+        VG_HIP(hipMalloc(&out->slots, sizeof(uint64_t) * 2 * (size_t)cap));
+        k_fill_u64<<<grid_of(2 * cap), 256, 0, st>>>(out->slots, 2 * cap, kEmpty);
         VG_HIP(hipGetLastError());
+        k_block_insert<<<grid_of(NB), 256, 0, st>>>(ublocks, bcounts, boffsets, codes_sorted, NB, out->slots, lg);
+        VG_HIP(hipGetLastError());
+        // 5. key bounding box
         int32_t h_box[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
-        VG_HIP(hipMemcpyAsync(d_flag, h_box, sizeof(h_box), hipMemcpyHostToDevice, st));
-        k_level_bbox<<<grid_of(out->V), 256, 0, st>>>(out->keys, out->V, d_flag);
+        VG_HIP(hipMemcpyAsync(d_small + 8, h_box, sizeof(h_box), hipMemcpyHostToDevice, st));
+        k_level_bbox<<<grid_of(V), 256, 0, st>>>(ukeys, V, d_small + 8);
         VG_HIP(hipGetLastError());
-        VG_HIP(hipMemcpyAsync(h_box, d_flag, sizeof(h_box), hipMemcpyDeviceToHost, st));
+        VG_HIP(hipMemcpyAsync(h_box, d_small + 8, sizeof(h_box), hipMemcpyDeviceToHost, st));
         VG_HIP(hipStreamSynchronize(st));
         for (int a = 0; a < 3; ++a) {
             out->kmin[a] = h_box[a];
             out->kmax[a] = h_box[3 + a];
         }
+    } else {
+        out->log2cap = 6;
+        VG_HIP(hipMalloc(&out->slots, sizeof(uint64_t) * 2 * 64));
+        k_fill_u64<<<1, 128, 0, st>>>(out->slots, 128, kEmpty);
+        VG_HIP(hipGetLastError());
     }
     VG_HIP(hipStreamSynchronize(st));
     return VG_OK;
@@ -218,21 +300,23 @@ vg_status export_level(vg_context* ctx, const Level& lv, int64_t* keys, double* 
     const int64_t V = lv.V;
     if (V == 0) return VG_OK;
     std::vector<uint64_t> k((size_t)V);
-    std::vector<int32_t> c((size_t)V);
+    std::vector<int32_t> c((size_t)V), l2r((size_t)V);
     std::vector<double> r((size_t)V * kRec64);
     VG_HIP(hipMemcpyAsync(k.data(), lv.keys, sizeof(uint64_t) * V, hipMemcpyDeviceToHost, st));
     VG_HIP(hipMemcpyAsync(c.data(), lv.counts, sizeof(int32_t) * V, hipMemcpyDeviceToHost, st));
+    VG_HIP(hipMemcpyAsync(l2r.data(), lv.lex2rec, sizeof(int32_t) * V, hipMemcpyDeviceToHost, st));
     VG_HIP(hipMemcpyAsync(r.data(), lv.rec64, sizeof(double) * kRec64 * V, hipMemcpyDeviceToHost, st));
     VG_HIP(hipStreamSynchronize(st));
     for (int64_t v = 0; v < V; ++v) {
         int64_t q[3];
         unpack_key(k[v], q);
+        const int64_t w = l2r[v];
         if (keys)
             for (int a = 0; a < 3; ++a) keys[3 * v + a] = q[a] + lv.K0[a];
         if (means)
-            for (int a = 0; a < 3; ++a) means[3 * v + a] = r[kRec64 * v + a];
+            for (int a = 0; a < 3; ++a) means[3 * v + a] = r[kRec64 * w + a];
         if (covs)
-            for (int a = 0; a < 6; ++a) covs[6 * v + a] = r[kRec64 * v + 3 + a];
+            for (int a = 0; a < 6; ++a) covs[6 * v + a] = r[kRec64 * w + 3 + a];
         if (counts) counts[v] = c[v];
     }
     return VG_OK;
@@ -245,6 +329,7 @@ void free_level(Level* lv) {
     if (lv->rec64) (void)hipFree(lv->rec64);
     if (lv->keys) (void)hipFree(lv->keys);
     if (lv->counts) (void)hipFree(lv->counts);
+    if (lv->lex2rec) (void)hipFree(lv->lex2rec);
     *lv = Level{};
 }
 
@@ -355,8 +440,8 @@ vg_status layout_source(vg_context* ctx, vg_source* s, const double* d_xyz, cons
     int32_t *idx = nullptr, *idx2 = nullptr;
     void* tmp = nullptr;
     size_t tb = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (uint64_t*)nullptr, (uint64_t*)nullptr, (int32_t*)nullptr,
-                                       (int32_t*)nullptr, (int)n, 0, 63);
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (uint64_t*)nullptr, (uint64_t*)nullptr, (int32_t*)nullptr,
+                                             (int32_t*)nullptr, (int)n, 0, 63);
     vg_status rc = VG_OK;
     hipError_t e = hipSuccess;
     do {

@@ -51,7 +51,7 @@ def test_voxelmap_matches_oracle_bit_exact(vg, c1, res):
         assert np.array_equal(m_d, m_o)     # same FP64 summation order -> identical bits
         assert np.array_equal(c_d, c_o)
         V, cap = m.info(l)
-        assert V == len(k_o) and cap >= 4 * V
+        assert V == len(k_o) and cap >= 64 and (cap & (cap - 1)) == 0
     m.close()
 
 

@@ -168,6 +168,13 @@ vg_status vg_linearize(vg_batch* batch, const double* poses, double* e, double* 
 /* Error only, with correspondences and W recomputed at the given poses. */
 vg_status vg_evaluate(vg_batch* batch, const double* poses, double* e);
 
+/* Overlap rate of every factor at its pose (GLIM Sec. IV-B and V: the
+ * fraction of source points that fall in an occupied voxel of the target,
+ * used to pick keyframes and submap pairs): overlap F x L, one fraction per
+ * level (points discarded by surface validation count as outside).  Runs the
+ * key/lookup path only. */
+vg_status vg_overlap(vg_batch* batch, const double* poses, double* overlap);
+
 /* Stream-ordered variants on device pointers (no host synchronization).
  * d_poses: F x 12 FP64.  d_out: F x 43 FP64 rows [e, H (36), b (6)];
  * d_inliers: F x L int64 or NULL.  d_e: F FP64. */
@@ -214,6 +221,30 @@ vg_status vg_correspondences(vg_batch* batch, const double* pose, int64_t factor
  * and the batch signature (precision, F, total points, levels, validation).
  * chosen (may be NULL) receives {block_threads, tile_points, blocks_per_cu}. */
 vg_status vg_batch_tune(vg_batch* batch, const double* poses, int32_t reps, int32_t* chosen);
+
+/* ---- pose graphs: two-node expansion and normal-equation assembly ------- */
+
+/* A graph of N pose nodes and F factors; factor f connects source node
+ * node_i[f] (whose cloud is transformed) and target node node_j[f], and its
+ * relative pose is T_f = T_j^-1 T_i (the pose the factor is linearized at).
+ * Sec. III-C: each factor's quadratic expands to H_ii = H, H_ij = -H A,
+ * H_jj = A^T H A, b_i = b, b_j = -A^T b with A = Ad(T_f^-1) (right
+ * perturbations of T_i and T_j, xi = [omega; v]).  The structure is a BSR
+ * matrix of 6x6 blocks: every diagonal block plus (i, j) and (j, i) for every
+ * factor, columns ascending within a row.  Node indices must be distinct and
+ * in [0, N). */
+typedef struct vg_graph vg_graph;
+vg_status vg_create_graph(vg_context* ctx, int64_t N, int64_t F, const int64_t* node_i, const int64_t* node_j,
+                          vg_graph** out);
+/* nnz_blocks (may be NULL); row_ptr N + 1 and col_idx nnz_blocks (host, may be NULL). */
+vg_status vg_graph_structure(const vg_graph* graph, int64_t* nnz_blocks, int64_t* row_ptr, int64_t* col_idx);
+/* Assemble on the context stream: d_poses F x 12 relative poses, d_lin F x 43
+ * rows [e, H, b] from vg_linearize_async; d_values nnz_blocks x 36 (row-major
+ * blocks), d_rhs N x 6.  Contributions are summed in factor order in FP64, so
+ * results are deterministic. */
+vg_status vg_graph_assemble_async(vg_graph* graph, const double* d_poses, const double* d_lin, double* d_values,
+                                  double* d_rhs);
+vg_status vg_graph_destroy(vg_graph* graph);
 
 /* Time the batched kernels on the context stream with HIP events: reps
  * launches of the tile kernel and of the factor reduction at device-resident

@@ -74,6 +74,7 @@ SIGNATURES = {
     "vg_batch_destroy": (C.c_int, [P]),
     "vg_linearize": (C.c_int, [P, P, P, P, P, P]),
     "vg_evaluate": (C.c_int, [P, P, P]),
+    "vg_overlap": (C.c_int, [P, P, P]),
     "vg_linearize_async": (C.c_int, [P, P, P, P]),
     "vg_evaluate_async": (C.c_int, [P, P, P]),
     "vg_backward_async": (C.c_int, [P, P, P, P, P, P, I32]),
@@ -81,6 +82,10 @@ SIGNATURES = {
     "vg_lm_run": (C.c_int, [P, P, I32, D, P, P, P]),
     "vg_correspondences": (C.c_int, [P, P, I64, P, P]),
     "vg_batch_tune": (C.c_int, [P, P, I32, P]),
+    "vg_create_graph": (C.c_int, [P, I64, I64, P, P, P]),
+    "vg_graph_structure": (C.c_int, [P, P, P, P]),
+    "vg_graph_assemble_async": (C.c_int, [P, P, P, P, P]),
+    "vg_graph_destroy": (C.c_int, [P]),
     "vg_batch_time_kernels": (C.c_int, [P, P, I32, P]),
 }
 

@@ -123,6 +123,7 @@ void hfree(void* p) {
 namespace vg {
 
 void set_error(const std::string& msg) { g_err = msg; }
+bool context_ok(const vg_context* c) { return ctx_ok(c); }
 
 vg_status hip_fail(hipError_t e, const char* what) {
     (void)hipGetLastError();
@@ -794,6 +795,25 @@ extern "C" vg_status vg_evaluate(vg_batch* b, const double* poses, double* e) {
     VG_HIP(hipMemcpyAsync(b->h_out, b->d_e, sizeof(double) * b->F, hipMemcpyDeviceToHost, st));
     VG_HIP(hipStreamSynchronize(st));
     std::memcpy(e, b->h_out, sizeof(double) * b->F);
+    return VG_OK;
+}
+
+extern "C" vg_status vg_overlap(vg_batch* b, const double* poses, double* overlap) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    if (overlap == nullptr) return invalid("overlap is NULL");
+    VG_TRY(check_poses(poses, b->F));
+    VG_HIP(hipSetDevice(b->ctx->device));
+    hipStream_t st = b->ctx->stream;
+    std::memcpy(b->h_poses, poses, sizeof(double) * 12 * b->F);
+    VG_HIP(hipMemcpyAsync(b->d_poses, b->h_poses, sizeof(double) * 12 * b->F, hipMemcpyHostToDevice, st));
+    const int32_t nt = (int32_t)b->h_tiles.size();
+    VG_TRY(launch_tiles(b, kCount, b->d_poses, 0, nt, b->grid, nullptr, nullptr, 0, 0, b->F));
+    // the per-level fractions land in d_out (F x L <= F x 43)
+    VG_TRY(launch_reduce(b, kCount, b->d_poses, 0, (int32_t)b->F, b->d_out, nullptr, nullptr, nullptr, nullptr));
+    VG_HIP(hipMemcpyAsync(b->h_out, b->d_out, sizeof(double) * b->L * b->F, hipMemcpyDeviceToHost, st));
+    VG_HIP(hipStreamSynchronize(st));
+    std::memcpy(overlap, b->h_out, sizeof(double) * b->L * b->F);
     return VG_OK;
 }
 

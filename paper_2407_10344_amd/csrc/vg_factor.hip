@@ -200,7 +200,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
     using T = typename PT<PREC>::T;
     constexpr int NW = BLOCK / 64;
     constexpr bool KAHAN = KH && (PREC == kC32);
-    constexpr int NT = (MODE == kLin) ? kTerms : (MODE == kEval ? 1 : 6);
+    constexpr int NT = (MODE == kLin) ? kTerms : (MODE == kBwd ? 6 : 1);
     __shared__ TileShared sh;
     __shared__ double s_red[NW][kRow];
     __shared__ int32_t s_tile;
@@ -428,6 +428,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 const int32_t v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
                 if (v < 0) continue;
                 inl[l] += 1;
+                if constexpr (MODE == kCount) continue;
                 if (!haveS) {
                     if constexpr (PREC == kC32) {
                         double R64[9], C64[6];
@@ -624,6 +625,11 @@ __global__ __launch_bounds__(64) void k_reduce(const FactorDesc* __restrict__ fa
         out[f] = s[0];
         return;
     }
+    if constexpr (MODE == kCount) {
+        // overlap rate: fraction of the source points that fall in an occupied voxel
+        for (int l = 0; l < F.L; ++l) out[(int64_t)F.L * f + l] = F.n > 0 ? s[kTerms + l] / (double)F.n : 0.0;
+        return;
+    }
     if constexpr (MODE == kBwd) {
         // g' = Bd^T g'' (rotate both halves back to the source frame), g = G^T g'
         double gw[3], gv[3], g[6];
@@ -816,6 +822,7 @@ vg_status launch_tiles(vg_batch* b, int mode, const double* d_poses, int32_t t0,
     return launch_tiles_t<M, kF64, false>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype);
     if (mode == kLin) { VG_DISPATCH(kLin) }
     if (mode == kEval) { VG_DISPATCH(kEval) }
+    if (mode == kCount) { VG_DISPATCH(kCount) }
     VG_DISPATCH(kBwd)
 #undef VG_DISPATCH
 }
@@ -837,6 +844,7 @@ vg_status launch_reduce(vg_batch* b, int mode, const double* d_poses, int32_t f0
     else reduce_t<M, kF64>(b, d_poses, f0, f1, d_out, d_inliers, d_grad_e, d_jr, d_grad_xi);
     if (mode == kLin) { VG_R(kLin) }
     else if (mode == kEval) { VG_R(kEval) }
+    else if (mode == kCount) { VG_R(kCount) }
     else { VG_R(kBwd) }
 #undef VG_R
     VG_HIP(hipGetLastError());

@@ -32,7 +32,7 @@ constexpr int kRec64 = 10;              // doubles per FP64 voxel record
 constexpr int kOutRow = 43;             // e, H (36), b (6)
 constexpr int kParts = 8;               // tile partitions = XCDs of an MI355X
 
-enum Mode { kLin = 0, kEval = 1, kBwd = 2 };
+enum Mode { kLin = 0, kEval = 1, kBwd = 2, kCount = 3 };
 enum Prec { kN32 = VG_FP32, kC32 = VG_FP32_COMPENSATED, kF64 = VG_FP64 };
 
 // ---------------------------------------------------------------- device descriptors
@@ -176,6 +176,7 @@ namespace vg {
 // ---------------------------------------------------------------- error state
 
 void set_error(const std::string& msg);
+bool context_ok(const vg_context* c);
 vg_status hip_fail(hipError_t e, const char* what);
 
 #define VG_HIP(call)                                        \

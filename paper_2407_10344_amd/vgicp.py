@@ -217,6 +217,13 @@ class FactorBatch:
         check(load().vg_evaluate(self.handle, _p(P), _p(e)))
         return e
 
+    def overlap(self, poses):
+        """Fraction of each factor's source points that fall in an occupied target voxel (F x L)."""
+        P = poses12(poses)
+        o = np.zeros((self.F, self.L))
+        check(load().vg_overlap(self.handle, _p(P), _p(o)))
+        return o
+
     def linearize_async(self, d_poses: torch.Tensor):
         d_poses = d_poses.contiguous()
         out = torch.empty((self.F, 43), dtype=torch.float64, device=d_poses.device)
@@ -281,6 +288,53 @@ class FactorBatch:
     def close(self):
         if self.handle:
             check(load().vg_batch_destroy(self.handle))
+            self.handle = None
+
+
+class Graph:
+    """Pose graph over N nodes: expands linearized factors into two-node blocks and
+    assembles the block-sparse (BSR, 6x6 blocks) normal equations on the device."""
+
+    def __init__(self, ctx: Context, N, node_i, node_j):
+        ni = np.ascontiguousarray(node_i, dtype=np.int64)
+        nj = np.ascontiguousarray(node_j, dtype=np.int64)
+        self.ctx = ctx
+        self.N, self.F = int(N), int(ni.shape[0])
+        h = C.c_void_p()
+        check(load().vg_create_graph(ctx.handle, self.N, self.F, _p(ni), _p(nj), C.byref(h)))
+        self.handle = h
+        nnzb = C.c_int64()
+        check(load().vg_graph_structure(self.handle, C.byref(nnzb), None, None))
+        self.nnzb = nnzb.value
+        self.row_ptr = np.zeros(self.N + 1, dtype=np.int64)
+        self.col_idx = np.zeros(max(self.nnzb, 1), dtype=np.int64)
+        check(load().vg_graph_structure(self.handle, None, _p(self.row_ptr), _p(self.col_idx)))
+        self.col_idx = self.col_idx[:self.nnzb]
+
+    def assemble(self, d_poses: torch.Tensor, d_lin: torch.Tensor):
+        """(values nnzb x 6 x 6, rhs N x 6) FP64 device tensors."""
+        values = torch.empty((self.nnzb, 6, 6), dtype=torch.float64, device=d_lin.device)
+        rhs = torch.empty((self.N, 6), dtype=torch.float64, device=d_lin.device)
+        d_poses = d_poses.contiguous()
+        d_lin = d_lin.contiguous()
+        self.ctx.enter()
+        check(load().vg_graph_assemble_async(self.handle, _tp(d_poses), _tp(d_lin), _tp(values), _tp(rhs)))
+        self.ctx.leave()
+        return values, rhs
+
+    def dense(self, values, rhs):
+        """Dense (6N x 6N, 6N) host copies, for checks on small graphs."""
+        v = values.cpu().numpy()
+        Hd = np.zeros((6 * self.N, 6 * self.N))
+        for r in range(self.N):
+            for k in range(self.row_ptr[r], self.row_ptr[r + 1]):
+                c = self.col_idx[k]
+                Hd[6 * r:6 * r + 6, 6 * c:6 * c + 6] = v[k]
+        return Hd, rhs.cpu().numpy().reshape(-1)
+
+    def close(self):
+        if self.handle:
+            check(load().vg_graph_destroy(self.handle))
             self.handle = None
 
 

@@ -254,3 +254,23 @@ def test_invalid_arguments(vg, c1):
     with pytest.raises(VGError, match="STATE"):
         list(maps.values())[0].close()                             # still used by the batch
     batch.close()
+
+
+def test_overlap_rate(vg, c2):
+    """Overlap rate (fraction of source points in an occupied target voxel, per level) on the
+    odometry batch: exact counts except points inside the 1e-5 m face band."""
+    vgicp, ctx = vg
+    maps, srcs, batch = vgicp.build_workload(ctx, c2)
+    poses = np.array(c2["poses"])
+    ov = batch.overlap(poses)
+    n = c2["sources"][0].n
+    for f in range(len(poses)):
+        of = oracle_factor(c2, f)
+        tr = of.linearize(poses[f], trace=True)
+        near = (tr["face"] < 1e-5).sum(axis=0)
+        dev_counts = np.rint(ov[f] * n).astype(np.int64)
+        assert np.all(np.abs(dev_counts - tr["inliers"]) <= near), (f, dev_counts, tr["inliers"], near)
+    # same counts as the linearization reports
+    _, _, _, inl = batch.linearize(poses)
+    assert np.array_equal(np.rint(ov * n).astype(np.int64), inl)
+    batch.close()

@@ -216,7 +216,9 @@ vg_status vg_correspondences(vg_batch* batch, const double* pose, int64_t factor
 /* Autotune the launch shape of a batch at representative poses (host F x 12):
  * every candidate (block threads x tile points x workgroups per CU) is timed
  * with HIP events over `reps` launches of the tile kernel and reduction; the
- * fastest is kept for this batch and, when the batch was created with a
+ * fastest is kept for this batch (candidates are visited in a fixed order of
+ * preference and a later one wins only when faster by more than 1.5 %, so the
+ * choice is stable under timing noise) and, when the batch was created with a
  * tune_cache path, appended to that file under a key made of the device name
  * and the batch signature (precision, F, total points, levels, validation).
  * chosen (may be NULL) receives {block_threads, tile_points, blocks_per_cu}. */

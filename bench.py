@@ -189,7 +189,7 @@ def _csvs(d, suffix):
     return sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
 
 
-def summarize_profiles(kt_dir, fetch_dir, write_dir, command, tile_points, workload):
+def summarize_profiles(kt_dir, fetch_dir, write_dir, command, tile_points, workload, warmup):
     """Text summary of one rocprofv3 kernel-trace run and two counter runs
     (FETCH_SIZE, WRITE_SIZE) of ``bench.py --profile-steps``.  The counters are
     scaled by what they read for the calibration kernels of known size that the
@@ -204,6 +204,13 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, command, tile_points, workl
         raise SystemExit("expected one tile-kernel row in the kernel stats, found %d" % len(tile))
     tile = tile[0]
 
+    # steady state: tile-kernel dispatches after the warm-up steps, from the kernel trace
+    durs = []
+    for f in _csvs(kt_dir, "_kernel_trace.csv"):
+        for r in csv.DictReader(open(f)):
+            if r["Kernel_Name"].startswith(tile_prefix):
+                durs.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    durs = [d for _, d in sorted(durs)][warmup:]
     shapes = set()
 
     def counters(d, name):
@@ -254,6 +261,8 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, command, tile_points, workl
         "tile_kernel_avg_ns: %.0f" % float(tile["AverageNs"]),
         "tile_kernel_min_ns: %s" % tile["MinNs"],
         "tile_kernel_max_ns: %s" % tile["MaxNs"],
+        "tile_kernel_steady_avg_ns: %.0f (%d dispatches after %d warm-up steps)" % (
+            sum(durs) / max(len(durs), 1), len(durs), warmup),
         "fetch_size_kib_per_dispatch: %.1f" % f_tile,
         "write_size_kib_per_dispatch: %.1f" % w_tile,
         "reduce_fetch_kib_per_dispatch: %.1f" % f_red,
@@ -293,7 +302,7 @@ def main():
     ap.add_argument("--lane-kahan", action="store_true", help="Kahan-compensated FP32 sums inside each lane")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
-                    help="only run this many batched steps (for profilers), print nothing else")
+                    help="only run --warmup + this many batched steps (for profilers), print no JSON")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the text summary of three rocprofv3 runs of --profile-steps and exit")
     ap.add_argument("--profile-command", action="append", default=[],
@@ -301,7 +310,8 @@ def main():
     args = ap.parse_args()
     if args.summarize_profiles:
         tag = "global submap batch, %d submaps" % args.submaps if args.workload == "global" else args.workload
-        sys.stdout.write(summarize_profiles(*args.summarize_profiles, args.profile_command, args.tile, tag))
+        sys.stdout.write(summarize_profiles(*args.summarize_profiles, args.profile_command, args.tile, tag,
+                                            args.warmup))
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)"
@@ -328,7 +338,7 @@ def main():
         log("autotuned %s in %.1f s" % (chosen, time.time() - t))
 
     if args.profile_steps:
-        for _ in range(args.profile_steps):
+        for _ in range(args.warmup + args.profile_steps):
             batch.linearize(poses)
         torch.cuda.synchronize()
         # kernels of known traffic, to scale the memory counters: a fill that
@@ -336,8 +346,8 @@ def main():
         src_t = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         total = src_t.sum()
         torch.cuda.synchronize()
-        log("profile run done: %d linearize steps; calibration: fill (write) and sum (read) of %d bytes, %s"
-            % (args.profile_steps, COPY_BYTES, float(total)))
+        log("profile run done: %d + %d warm-up linearize steps; calibration: fill (write) and sum (read) of %d bytes, %s"
+            % (args.profile_steps, args.warmup, COPY_BYTES, float(total)))
         return
 
     for _ in range(args.warmup):
@@ -400,6 +410,7 @@ def main():
                                                   "batched_speedup": value / plain_rate},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
+                     "dram_frac": None if traffic is None else traffic / (tk["tile_kernel_ms"] * 1e-3) / HBM_PEAK,
                      "kernel": "k_tiles<lin,%s>" % args.precision, "kernel_ms": tk["tile_kernel_ms"],
                      "reduce_ms": tk["reduce_ms"], "algorithmic_bytes": B_alg},
         "cpu_baseline": cpu,

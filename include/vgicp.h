@@ -145,6 +145,49 @@ vg_status vg_create_source(vg_context* ctx, const double* xyz, const double* cov
 vg_status vg_source_set_points_async(vg_source* src, const void* d_xyz, int32_t dtype);
 vg_status vg_source_destroy(vg_source* src);
 
+/* ---- preprocessing (Sec. IV-A; Sec. III-C, Preprocessing) ---------------- */
+
+/* A preprocessed frame resident on the device: downsampled points with their
+ * k nearest neighbours, regularised covariances and oriented normals. */
+typedef struct vg_cloud vg_cloud;
+
+/* Sec. IV-A: a raw frame is downsampled, then each kept point gets its k
+ * nearest neighbours (exact search) and, from them, a covariance (Sec. III-C,
+ * Preprocessing).  The steps as computed here:
+ *   1. voxel-grid downsampling: every input point falls in voxel floor(x / r);
+ *      each occupied voxel gives one point, the mean of its input points
+ *      (FP64 sums in input order); outputs in ascending lexicographic order of
+ *      the voxel key (|floor(x / r)| < 2^20 per axis, else VG_ERR_KEY_RANGE);
+ *   2. exact k-NN among the downsampled points, the point itself included;
+ *      squared distances in FP64 as (dx*dx + dy*dy) + dz*dz with each operation
+ *      rounded, ties by the smaller index; fewer than k points: all of them,
+ *      the rest of the row padded with -1;
+ *   3. covariance (1/k') sum (p - pbar)(p - pbar)^T over the k' found
+ *      neighbours; its eigenvalues are replaced by (1e-3, 1, 1) in ascending
+ *      order (plane-to-plane regularisation), i.e. C = I - 0.999 n n^T;
+ *   4. normal n: eigenvector of the smallest eigenvalue (FP64 Jacobi), oriented
+ *      so that n . (sensor - p) >= 0.
+ * xyz: n x 3 host FP64 (n >= 0, finite); r > 0; 1 <= k <= 32; sensor: 3 host
+ * doubles (the frame's sensor position).  Synchronous (the output size is read
+ * back).  Errors: VG_ERR_INVALID_ARG, VG_ERR_KEY_RANGE, VG_ERR_OOM, VG_ERR_HIP. */
+vg_status vg_preprocess(vg_context* ctx, const double* xyz, int64_t n, double r, int32_t k, const double* sensor,
+                        vg_cloud** out);
+/* Number of downsampled points and the neighbour count k of a cloud. */
+vg_status vg_cloud_info(const vg_cloud* cloud, int64_t* n_points, int32_t* k);
+/* Copy a cloud to the host; any output may be NULL.  xyz m x 3, cov m x 6
+ * (regularised), cov_raw m x 6 (before regularisation), normals m x 3,
+ * counts m (input points per voxel), nbr m x k (indices into the cloud),
+ * nbr_d2 m x k (squared distances, +inf where padded). */
+vg_status vg_cloud_export(const vg_cloud* cloud, double* xyz, double* cov, double* cov_raw, double* normals,
+                          int64_t* counts, int32_t* nbr, double* nbr_d2);
+/* A source cloud / voxel map made from a preprocessed cloud without leaving the
+ * device (same semantics as vg_create_source with normals / vg_build_voxelmap
+ * on the cloud's FP64 points and regularised covariances). */
+vg_status vg_create_source_from_cloud(vg_context* ctx, const vg_cloud* cloud, vg_source** out);
+vg_status vg_build_voxelmap_from_cloud(vg_context* ctx, const vg_cloud* cloud, const double* resolutions,
+                                       int32_t L, vg_voxelmap** out);
+vg_status vg_cloud_destroy(vg_cloud* cloud);
+
 /* ---- factor batches (Sec. III-C, Implementation) ----------------------- */
 
 /* A batch of F factors; factor f matches src[f] into tgt[f].

@@ -18,7 +18,9 @@ normalisation nor the regularisation; the readings taken here:
 * normal n: eigenvector of the smallest eigenvalue, oriented so that
   n . (sensor - p) >= 0.
 
-Plain numpy: no blocking beyond what memory needs, no acceleration structure.
+Plain numpy, no blocking beyond what memory needs.  knn() is brute force;
+knn_tree() takes the neighbours from scipy's k-d tree (a library search
+primitive, pinned against knn()) for clouds where brute force is too slow.
 """
 
 from __future__ import annotations
@@ -70,6 +72,28 @@ def knn(points, k, queries=None):
     return idx, d2
 
 
+def knn_tree(points, k):
+    """The same k nearest neighbours from scipy's k-d tree (a library search
+    primitive; exact).  Rows are ordered by (distance, index) like knn(); it
+    differs from knn() only where distances tie at the k-th place, which
+    continuous random data does not produce.  Used where brute force is too slow."""
+    from scipy.spatial import cKDTree
+    P = np.asarray(points, dtype=np.float64)
+    kk = min(k, len(P))
+    idx = np.full((len(P), k), -1, np.int64)
+    d2 = np.full((len(P), k), np.inf)
+    if kk == 0:
+        return idx, d2
+    _, nb = cKDTree(P).query(P, k=kk)
+    nb = nb.reshape(len(P), kk)
+    for row in range(len(P)):
+        d = sqdist(P[row], P[nb[row]])
+        o = np.lexsort((nb[row], d))
+        idx[row, :kk] = nb[row][o]
+        d2[row, :kk] = d[o]
+    return idx, d2
+
+
 def covariance(points, nbr):
     """(1/k) sum (p - pbar)(p - pbar)^T over the valid neighbours of each row."""
     P = np.asarray(points, dtype=np.float64)
@@ -96,10 +120,11 @@ def regularize(C, xyz, sensor):
     return Creg, n, w
 
 
-def preprocess(xyz, r, k, sensor):
-    """Downsample, k-NN, covariance, regularisation.  Returns a dict of the stages."""
+def preprocess(xyz, r, k, sensor, search=None):
+    """Downsample, k-NN, covariance, regularisation.  Returns a dict of the stages.
+    search: None = brute force (knn), "tree" = knn_tree."""
     c, keys, cnt = downsample(xyz, r)
-    idx, d2 = knn(c, k)
+    idx, d2 = knn_tree(c, k) if search == "tree" else knn(c, k)
     C = covariance(c, idx)
     Creg, n, w = regularize(C, c, sensor)
     return {"xyz": c, "keys": keys, "counts": cnt, "nbr": idx, "d2": d2, "cov_raw": C, "cov": Creg,

@@ -10,7 +10,8 @@ __version__ = "1.0.0"
 
 
 def __getattr__(name):
-    if name in ("Context", "VoxelMap", "Source", "FactorBatch", "build_workload", "poses12", "pose4x4"):
+    if name in ("Context", "VoxelMap", "Source", "Cloud", "FactorBatch", "Graph", "build_workload", "poses12",
+                "pose4x4"):
         from . import vgicp
         return getattr(vgicp, name)
     if name in ("VGICPCost",):

@@ -69,6 +69,12 @@ SIGNATURES = {
     "vg_create_source": (C.c_int, [P, P, P, P, I64, P]),
     "vg_source_set_points_async": (C.c_int, [P, P, I32]),
     "vg_source_destroy": (C.c_int, [P]),
+    "vg_preprocess": (C.c_int, [P, P, I64, D, I32, P, P]),
+    "vg_cloud_info": (C.c_int, [P, P, P]),
+    "vg_cloud_export": (C.c_int, [P, P, P, P, P, P, P, P]),
+    "vg_create_source_from_cloud": (C.c_int, [P, P, P]),
+    "vg_build_voxelmap_from_cloud": (C.c_int, [P, P, P, I32, P]),
+    "vg_cloud_destroy": (C.c_int, [P]),
     "vg_create_factor_batch": (C.c_int, [P, I64, P, P, P, P, P]),
     "vg_batch_info": (C.c_int, [P, P, P, P, P, P]),
     "vg_batch_destroy": (C.c_int, [P]),

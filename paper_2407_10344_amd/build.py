@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libvgicp.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["vg_api.cpp", "vg_voxelmap.hip", "vg_factor.hip", "vg_lm.hip", "vg_graph.hip"]
+SOURCES = ["vg_api.cpp", "vg_voxelmap.hip", "vg_factor.hip", "vg_lm.hip", "vg_graph.hip", "vg_preprocess.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 

@@ -194,6 +194,38 @@ extern "C" vg_status vg_context_destroy(vg_context* ctx) {
 
 // ============================================================================ voxel maps
 
+// Voxel map from device FP64 arrays; first = host copy of point 0 (the origin).
+static vg_status make_voxelmap(vg_context* ctx, const double* d_xyz, const double* d_cov, int64_t n,
+                               const double* resolutions, int32_t L, const double* first, vg_voxelmap** out) {
+    auto* m = new vg_voxelmap();
+    m->ctx = ctx;
+    m->L = L;
+    const double rmax = resolutions[L - 1];
+    for (int a = 0; a < 3; ++a) m->origin[a] = (n > 0) ? rmax * std::nearbyint(first[a] / rmax) : 0.0;
+    vg_status st = VG_OK;
+    for (int l = 0; l < L && st == VG_OK; ++l)
+        st = build_level(ctx, d_xyz, d_cov, n, resolutions[l], m->origin, &m->lv[l]);
+    if (st != VG_OK) {
+        for (int l = 0; l < kMaxLevels; ++l) free_level(&m->lv[l]);
+        delete m;
+        return st;
+    }
+    m->magic = kMapMagic;
+    *out = m;
+    return VG_OK;
+}
+
+static vg_status check_resolutions(const double* resolutions, int32_t L) {
+    if (L < 1 || L > kMaxLevels) return invalid("L must be in 1..4");
+    if (resolutions == nullptr) return invalid("resolutions is NULL");
+    for (int l = 0; l < L; ++l) {
+        const double r = resolutions[l];
+        if (!(std::isfinite(r) && r > 0.0 && is_pow2(r))) return invalid("each resolution must be a positive power of two");
+        if (l > 0 && !(r > resolutions[l - 1])) return invalid("resolutions must be strictly ascending");
+    }
+    return VG_OK;
+}
+
 extern "C" vg_status vg_build_voxelmap(vg_context* ctx, const double* xyz, const double* cov, int64_t n,
                                        const double* resolutions, int32_t L, vg_voxelmap** out) {
     g_err.clear();
@@ -203,13 +235,7 @@ extern "C" vg_status vg_build_voxelmap(vg_context* ctx, const double* xyz, const
     if (n < 0) return invalid("n < 0");
     if (n > 0 && (xyz == nullptr || cov == nullptr)) return invalid("xyz or cov is NULL");
     if (n >= (int64_t)1 << 31) return invalid("n must be below 2^31");
-    if (L < 1 || L > kMaxLevels) return invalid("L must be in 1..4");
-    if (resolutions == nullptr) return invalid("resolutions is NULL");
-    for (int l = 0; l < L; ++l) {
-        const double r = resolutions[l];
-        if (!(std::isfinite(r) && r > 0.0 && is_pow2(r))) return invalid("each resolution must be a positive power of two");
-        if (l > 0 && !(r > resolutions[l - 1])) return invalid("resolutions must be strictly ascending");
-    }
+    VG_TRY(check_resolutions(resolutions, L));
     if (n > 0 && !finite_all(xyz, 3 * n)) return invalid("xyz has non-finite values");
     if (n > 0 && !finite_all(cov, 6 * n)) return invalid("cov has non-finite values");
     for (int64_t i = 0; i < n; ++i)
@@ -218,11 +244,6 @@ extern "C" vg_status vg_build_voxelmap(vg_context* ctx, const double* xyz, const
             return VG_ERR_NOT_SPD;
         }
     VG_HIP(hipSetDevice(ctx->device));
-    auto* m = new vg_voxelmap();
-    m->ctx = ctx;
-    m->L = L;
-    const double rmax = resolutions[L - 1];
-    for (int a = 0; a < 3; ++a) m->origin[a] = (n > 0) ? rmax * std::nearbyint(xyz[a] / rmax) : 0.0;
     double *d_xyz = nullptr, *d_cov = nullptr;
     vg_status st = VG_OK;
     do {
@@ -238,19 +259,11 @@ extern "C" vg_status vg_build_voxelmap(vg_context* ctx, const double* xyz, const
             st = hip_fail(e, "voxelmap upload");
             break;
         }
-        for (int l = 0; l < L && st == VG_OK; ++l)
-            st = build_level(ctx, d_xyz, d_cov, n, resolutions[l], m->origin, &m->lv[l]);
+        st = make_voxelmap(ctx, d_xyz, d_cov, n, resolutions, L, xyz, out);
     } while (0);
     dfree(d_xyz);
     dfree(d_cov);
-    if (st != VG_OK) {
-        for (int l = 0; l < kMaxLevels; ++l) free_level(&m->lv[l]);
-        delete m;
-        return st;
-    }
-    m->magic = kMapMagic;
-    *out = m;
-    return VG_OK;
+    return st;
 }
 
 extern "C" vg_status vg_voxelmap_info(const vg_voxelmap* map, int32_t level, int64_t* n_voxels, int64_t* capacity) {
@@ -304,6 +317,43 @@ static void free_source(vg_source* s) {
     dfree(s->perm);
 }
 
+// Source from device FP64 arrays (caller order); first = host copy of point 0.
+static vg_status make_source(vg_context* ctx, const double* d_xyz, const double* d_cov, const double* d_nrm,
+                             bool has_normals, int64_t n, const double* first, vg_source** out) {
+    auto* s = new vg_source();
+    s->ctx = ctx;
+    s->n = n;
+    s->n_pad = ((n + kChunk - 1) / kChunk) * kChunk;
+    s->n_chunks = s->n_pad / kChunk;
+    s->has_normals = has_normals;
+    for (int a = 0; a < 3; ++a) s->origin[a] = (n > 0) ? std::nearbyint(first[a]) : 0.0;
+    const int64_t np = s->n_pad;
+    vg_status st = VG_OK;
+    do {
+        if ((st = dev_alloc(&s->dxyz, 3 * np)) != VG_OK) break;
+        if ((st = dev_alloc(&s->cov, 6 * np)) != VG_OK) break;
+        if ((st = dev_alloc(&s->anchor, 3 * s->n_chunks)) != VG_OK) break;
+        if ((st = dev_alloc(&s->axyz, 3 * np)) != VG_OK) break;
+        if ((st = dev_alloc(&s->xyz64, 3 * np)) != VG_OK) break;
+        if ((st = dev_alloc(&s->cov64, 6 * np)) != VG_OK) break;
+        if ((st = dev_alloc(&s->perm, np)) != VG_OK) break;
+        if (has_normals) {
+            if ((st = dev_alloc(&s->nrm, 3 * np)) != VG_OK) break;
+            if ((st = dev_alloc(&s->nrm64, 3 * np)) != VG_OK) break;
+        }
+        if (n == 0) break;
+        st = layout_source(ctx, s, d_xyz, d_cov, d_nrm);
+    } while (0);
+    if (st != VG_OK) {
+        free_source(s);
+        delete s;
+        return st;
+    }
+    s->magic = kSrcMagic;
+    *out = s;
+    return VG_OK;
+}
+
 extern "C" vg_status vg_create_source(vg_context* ctx, const double* xyz, const double* cov, const double* normals,
                                       int64_t n, vg_source** out) {
     g_err.clear();
@@ -322,29 +372,13 @@ extern "C" vg_status vg_create_source(vg_context* ctx, const double* xyz, const 
             return VG_ERR_NOT_SPD;
         }
     VG_HIP(hipSetDevice(ctx->device));
-    auto* s = new vg_source();
-    s->ctx = ctx;
-    s->n = n;
-    s->n_pad = ((n + kChunk - 1) / kChunk) * kChunk;
-    s->n_chunks = s->n_pad / kChunk;
-    s->has_normals = normals != nullptr;
-    for (int a = 0; a < 3; ++a) s->origin[a] = (n > 0) ? std::nearbyint(xyz[a]) : 0.0;
-    const int64_t np = s->n_pad;
     double *d_xyz = nullptr, *d_cov = nullptr, *d_nrm = nullptr;
     vg_status st = VG_OK;
     do {
-        if ((st = dev_alloc(&s->dxyz, 3 * np)) != VG_OK) break;
-        if ((st = dev_alloc(&s->cov, 6 * np)) != VG_OK) break;
-        if ((st = dev_alloc(&s->anchor, 3 * s->n_chunks)) != VG_OK) break;
-        if ((st = dev_alloc(&s->axyz, 3 * np)) != VG_OK) break;
-        if ((st = dev_alloc(&s->xyz64, 3 * np)) != VG_OK) break;
-        if ((st = dev_alloc(&s->cov64, 6 * np)) != VG_OK) break;
-        if ((st = dev_alloc(&s->perm, np)) != VG_OK) break;
-        if (normals) {
-            if ((st = dev_alloc(&s->nrm, 3 * np)) != VG_OK) break;
-            if ((st = dev_alloc(&s->nrm64, 3 * np)) != VG_OK) break;
+        if (n == 0) {
+            st = make_source(ctx, nullptr, nullptr, nullptr, normals != nullptr, 0, xyz, out);
+            break;
         }
-        if (n == 0) break;
         if ((st = dev_alloc(&d_xyz, 3 * n)) != VG_OK) break;
         if ((st = dev_alloc(&d_cov, 6 * n)) != VG_OK) break;
         if (normals && (st = dev_alloc(&d_nrm, 3 * n)) != VG_OK) break;
@@ -356,19 +390,12 @@ extern "C" vg_status vg_create_source(vg_context* ctx, const double* xyz, const 
             st = hip_fail(e, "source upload");
             break;
         }
-        st = layout_source(ctx, s, d_xyz, d_cov, d_nrm);
+        st = make_source(ctx, d_xyz, d_cov, d_nrm, normals != nullptr, n, xyz, out);
     } while (0);
     dfree(d_xyz);
     dfree(d_cov);
     dfree(d_nrm);
-    if (st != VG_OK) {
-        free_source(s);
-        delete s;
-        return st;
-    }
-    s->magic = kSrcMagic;
-    *out = s;
-    return VG_OK;
+    return st;
 }
 
 extern "C" vg_status vg_source_set_points_async(vg_source* src, const void* d_xyz, int32_t dtype) {
@@ -389,6 +416,119 @@ extern "C" vg_status vg_source_destroy(vg_source* src) {
     free_source(src);
     src->magic = 0;
     delete src;
+    return VG_OK;
+}
+
+// ============================================================================ preprocessed clouds
+
+static constexpr uint32_t kCloudMagic = 0xC10D0001u;
+static bool cloud_ok(const vg_cloud* c) { return c != nullptr && c->magic == kCloudMagic; }
+
+extern "C" vg_status vg_preprocess(vg_context* ctx, const double* xyz, int64_t n, double r, int32_t k,
+                                   const double* sensor, vg_cloud** out) {
+    g_err.clear();
+    if (!ctx_ok(ctx)) return state_err("invalid context");
+    if (out == nullptr) return invalid("out is NULL");
+    *out = nullptr;
+    if (n < 0) return invalid("n < 0");
+    if (n >= (int64_t)1 << 31) return invalid("n must be below 2^31");
+    if (n > 0 && xyz == nullptr) return invalid("xyz is NULL");
+    if (!(std::isfinite(r) && r > 0.0)) return invalid("r must be positive and finite");
+    if (k < 1 || k > 32) return invalid("k must be in 1..32");
+    if (sensor == nullptr || !finite_all(sensor, 3)) return invalid("sensor must be 3 finite values");
+    if (n > 0 && !finite_all(xyz, 3 * n)) return invalid("xyz has non-finite values");
+    VG_HIP(hipSetDevice(ctx->device));
+    double* d_xyz = nullptr;
+    auto* c = new vg_cloud();
+    c->ctx = ctx;
+    vg_status st = VG_OK;
+    do {
+        if ((st = dev_alloc(&d_xyz, 3 * n)) != VG_OK) break;
+        if (n > 0) {
+            hipError_t e = hipMemcpyAsync(d_xyz, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, ctx->stream);
+            if (e != hipSuccess) {
+                st = hip_fail(e, "frame upload");
+                break;
+            }
+        }
+        st = preprocess_frame(ctx, d_xyz, n, r, k, sensor, c);
+    } while (0);
+    dfree(d_xyz);
+    if (st != VG_OK) {
+        free_cloud(c);
+        delete c;
+        return st;
+    }
+    c->magic = kCloudMagic;
+    *out = c;
+    return VG_OK;
+}
+
+extern "C" vg_status vg_cloud_info(const vg_cloud* cloud, int64_t* n_points, int32_t* k) {
+    g_err.clear();
+    if (!cloud_ok(cloud)) return state_err("invalid cloud");
+    if (n_points) *n_points = cloud->m;
+    if (k) *k = cloud->k;
+    return VG_OK;
+}
+
+extern "C" vg_status vg_cloud_export(const vg_cloud* cloud, double* xyz, double* cov, double* cov_raw,
+                                     double* normals, int64_t* counts, int32_t* nbr, double* nbr_d2) {
+    g_err.clear();
+    if (!cloud_ok(cloud)) return state_err("invalid cloud");
+    VG_HIP(hipSetDevice(cloud->ctx->device));
+    hipStream_t st = cloud->ctx->stream;
+    const int64_t m = cloud->m, k = cloud->k;
+    if (m == 0) return VG_OK;
+    if (xyz) VG_HIP(hipMemcpyAsync(xyz, cloud->xyz, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, st));
+    if (cov) VG_HIP(hipMemcpyAsync(cov, cloud->cov, sizeof(double) * 6 * m, hipMemcpyDeviceToHost, st));
+    if (cov_raw) VG_HIP(hipMemcpyAsync(cov_raw, cloud->cov_raw, sizeof(double) * 6 * m, hipMemcpyDeviceToHost, st));
+    if (normals) VG_HIP(hipMemcpyAsync(normals, cloud->nrm, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, st));
+    if (nbr) VG_HIP(hipMemcpyAsync(nbr, cloud->nbr, sizeof(int32_t) * m * k, hipMemcpyDeviceToHost, st));
+    if (nbr_d2) VG_HIP(hipMemcpyAsync(nbr_d2, cloud->d2, sizeof(double) * m * k, hipMemcpyDeviceToHost, st));
+    std::vector<int32_t> c32;
+    if (counts) {
+        c32.resize(m);
+        VG_HIP(hipMemcpyAsync(c32.data(), cloud->counts, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
+    }
+    VG_HIP(hipStreamSynchronize(st));
+    if (counts)
+        for (int64_t i = 0; i < m; ++i) counts[i] = c32[i];
+    return VG_OK;
+}
+
+extern "C" vg_status vg_create_source_from_cloud(vg_context* ctx, const vg_cloud* cloud, vg_source** out) {
+    g_err.clear();
+    if (!ctx_ok(ctx)) return state_err("invalid context");
+    if (!cloud_ok(cloud)) return state_err("invalid cloud");
+    if (cloud->ctx != ctx) return state_err("cloud from another context");
+    if (out == nullptr) return invalid("out is NULL");
+    *out = nullptr;
+    VG_HIP(hipSetDevice(ctx->device));
+    return make_source(ctx, cloud->xyz, cloud->cov, cloud->nrm, true, cloud->m, cloud->first, out);
+}
+
+extern "C" vg_status vg_build_voxelmap_from_cloud(vg_context* ctx, const vg_cloud* cloud, const double* resolutions,
+                                                  int32_t L, vg_voxelmap** out) {
+    g_err.clear();
+    if (!ctx_ok(ctx)) return state_err("invalid context");
+    if (!cloud_ok(cloud)) return state_err("invalid cloud");
+    if (cloud->ctx != ctx) return state_err("cloud from another context");
+    if (out == nullptr) return invalid("out is NULL");
+    *out = nullptr;
+    VG_TRY(check_resolutions(resolutions, L));
+    VG_HIP(hipSetDevice(ctx->device));
+    return make_voxelmap(ctx, cloud->xyz, cloud->cov, cloud->m, resolutions, L, cloud->first, out);
+}
+
+extern "C" vg_status vg_cloud_destroy(vg_cloud* cloud) {
+    g_err.clear();
+    if (!cloud_ok(cloud)) return state_err("invalid cloud");
+    (void)hipSetDevice(cloud->ctx->device);
+    (void)hipStreamSynchronize(cloud->ctx->stream);
+    free_cloud(cloud);
+    cloud->magic = 0;
+    delete cloud;
     return VG_OK;
 }
 

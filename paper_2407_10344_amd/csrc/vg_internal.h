@@ -136,6 +136,22 @@ struct vg_source {
     uint32_t magic = 0;
 };
 
+// A preprocessed frame (downsampled points, neighbours, covariances, normals).
+struct vg_cloud {
+    vg_context* ctx = nullptr;
+    int64_t m = 0;              // downsampled points
+    int32_t k = 0;              // neighbours per point
+    double* xyz = nullptr;      // m x 3
+    double* cov = nullptr;      // m x 6 regularised
+    double* cov_raw = nullptr;  // m x 6 neighbour covariance
+    double* nrm = nullptr;      // m x 3
+    int32_t* counts = nullptr;  // m input points per voxel
+    int32_t* nbr = nullptr;     // m x k
+    double* d2 = nullptr;       // m x k
+    double first[3] = {0, 0, 0};// host copy of point 0 (origins of sources / maps made from the cloud)
+    uint32_t magic = 0;
+};
+
 struct vg_batch {
     vg_context* ctx = nullptr;
     int64_t F = 0;
@@ -192,6 +208,11 @@ vg_status build_level(vg_context* ctx, const double* d_xyz, const double* d_cov,
 vg_status export_level(vg_context* ctx, const Level& lv, int64_t* keys, double* means, double* covs,
                        int64_t* counts);
 void free_level(Level* lv);
+
+// frame preprocessing: d_xyz n x 3 FP64 device input; fills every array of *out
+vg_status preprocess_frame(vg_context* ctx, const double* d_xyz, int64_t n, double r, int k, const double sensor[3],
+                           vg_cloud* out);
+void free_cloud(vg_cloud* c);
 
 vg_status layout_source(vg_context* ctx, vg_source* s, const double* d_xyz, const double* d_cov,
                         const double* d_nrm);

@@ -101,6 +101,19 @@ class VoxelMap:
         check(load().vg_build_voxelmap(ctx.handle, _p(xyz), _p(cov), xyz.shape[0], _p(res), self.L, C.byref(h)))
         self.handle = h
 
+    @classmethod
+    def from_cloud(cls, ctx: Context, cloud: "Cloud", resolutions):
+        """Voxel map of a preprocessed cloud, built without leaving the device."""
+        res = _f64(resolutions, (-1,))
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self.L = int(res.shape[0])
+        self.resolutions = res.tolist()
+        h = C.c_void_p()
+        check(load().vg_build_voxelmap_from_cloud(ctx.handle, cloud.handle, _p(res), self.L, C.byref(h)))
+        self.handle = h
+        return self
+
     def info(self, level=0):
         V, cap = C.c_int64(), C.c_int64()
         check(load().vg_voxelmap_info(self.handle, level, C.byref(V), C.byref(cap)))
@@ -137,6 +150,17 @@ class Source:
         check(load().vg_create_source(ctx.handle, _p(xyz), _p(cov), _p(nrm), self.n, C.byref(h)))
         self.handle = h
 
+    @classmethod
+    def from_cloud(cls, ctx: Context, cloud: "Cloud"):
+        """Source made from a preprocessed cloud (with its normals), on the device."""
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self.n = cloud.n
+        h = C.c_void_p()
+        check(load().vg_create_source_from_cloud(ctx.handle, cloud.handle, C.byref(h)))
+        self.handle = h
+        return self
+
     def set_points(self, xyz: torch.Tensor):
         """Replace positions from a device tensor (n x 3, float32 or float64, caller order)."""
         assert xyz.is_cuda and xyz.shape == (self.n, 3)
@@ -152,6 +176,36 @@ class Source:
     def close(self):
         if self.handle:
             check(load().vg_source_destroy(self.handle))
+            self.handle = None
+
+
+class Cloud:
+    """A preprocessed frame on the device: voxel-grid downsampling, exact k-NN,
+    regularised neighbour covariances and normals oriented towards the sensor."""
+
+    def __init__(self, ctx: Context, xyz, r, k=10, sensor=(0.0, 0.0, 0.0)):
+        xyz = _f64(xyz, (-1, 3))
+        s = _f64(sensor, (3,))
+        self.ctx = ctx
+        h = C.c_void_p()
+        check(load().vg_preprocess(ctx.handle, _p(xyz), xyz.shape[0], float(r), int(k), _p(s), C.byref(h)))
+        self.handle = h
+        m, kk = C.c_int64(), C.c_int32()
+        check(load().vg_cloud_info(self.handle, C.byref(m), C.byref(kk)))
+        self.n, self.k = m.value, kk.value
+
+    def export(self):
+        m, k = max(self.n, 1), self.k
+        out = {"xyz": np.zeros((m, 3)), "cov": np.zeros((m, 6)), "cov_raw": np.zeros((m, 6)),
+               "normals": np.zeros((m, 3)), "counts": np.zeros(m, dtype=np.int64),
+               "nbr": np.zeros((m, k), dtype=np.int32), "d2": np.zeros((m, k))}
+        check(load().vg_cloud_export(self.handle, _p(out["xyz"]), _p(out["cov"]), _p(out["cov_raw"]),
+                                     _p(out["normals"]), _p(out["counts"]), _p(out["nbr"]), _p(out["d2"])))
+        return {key: v[:self.n] for key, v in out.items()}
+
+    def close(self):
+        if self.handle:
+            check(load().vg_cloud_destroy(self.handle))
             self.handle = None
 
 

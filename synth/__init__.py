@@ -3,9 +3,11 @@
 This package is shared by the FP64 oracle tests and by the device path.  It
 holds none of the factor's arithmetic (no voxelization, no transform of a
 source cloud by a factor pose, no residuals): it only produces point clouds,
-their per-point k-NN covariances and normals (the preprocessing of Sec. III-C
-that happens before a factor exists), and the relative poses at which factors
-are linearized.
+their per-point k-NN covariances and normals (computed with scipy's k-d tree,
+as input construction for the factor path), raw LiDAR frames, and the
+relative poses at which factors are linearized.  The device preprocessing
+(downsampling, k-NN, covariances) and its oracle use none of this package's
+covariance code: they start from the raw frames.
 
 Every array that crosses into the oracle or the device library is FP64 whose
 values are exactly ``origin + float32 offset`` (positions) or exactly float32
@@ -23,6 +25,9 @@ from .configs import (
     config5,
     tiny_lattice_pair,
     random_pose,
+    raw_frame,
+    thin_wall_pair,
+    local_mapping,
 )
 
 __all__ = [
@@ -37,4 +42,7 @@ __all__ = [
     "config5",
     "tiny_lattice_pair",
     "random_pose",
+    "raw_frame",
+    "thin_wall_pair",
+    "local_mapping",
 ]

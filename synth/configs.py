@@ -205,13 +205,9 @@ def lidar_frame(rng, T_sensor, lo, hi, dirs, rmin=1.0, rmax=80.0, noise=0.02):
     return pts + rng.normal(0.0, noise, pts.shape)
 
 
-def config2(seed=2, n_keyframes=20, resolutions=(0.25, 0.5, 1.0, 2.0), n_rings=32, n_az=1000,
-            workers=-1):
-    """One new 32-ring frame matched against 20 keyframes spaced 1 m apart (4-level maps)."""
-    scene_rng, traj_rng, noise_rng, pose_rng = (np.random.default_rng(s) for s in
-                                                np.random.SeedSequence(seed).spawn(4))
-    s, x, y, yaw = _smooth_trajectory(traj_rng, float(n_keyframes))
-    path = np.stack([x, y], axis=1)
+def _urban_scene(scene_rng, path):
+    """Ground + 200 boxes (footprint 2-15 m, height 2-25 m) in [-75, 75]^2 m, kept
+    3 m clear of the trajectory, and 40 m perimeter walls so most rays return."""
     tree = cKDTree(path)
     boxes_lo, boxes_hi = [], []
     while len(boxes_lo) < 200:
@@ -231,12 +227,90 @@ def config2(seed=2, n_keyframes=20, resolutions=(0.25, 0.5, 1.0, 2.0), n_rings=3
                 break
     lo = np.array(boxes_lo)
     hi = np.array(boxes_hi)
-    # perimeter walls so most rays return
     W, th, H = 70.0, 1.0, 40.0
     walls_lo = np.array([[-W - th, -W - th, 0], [W, -W - th, 0], [-W - th, -W - th, 0], [-W - th, W, 0]])
     walls_hi = np.array([[-W, W + th, H], [W + th, W + th, H], [W + th, -W, H], [W + th, W + th, H]])
-    lo = np.concatenate([lo, walls_lo])
-    hi = np.concatenate([hi, walls_hi])
+    return np.concatenate([lo, walls_lo]), np.concatenate([hi, walls_hi])
+
+
+def raw_frame(seed=6, n_rings=128, n_az=1024, elev=(-45.0, 45.0)):
+    """One raw sweep of a 128-ring, 90-degree-FOV spinning LiDAR in the urban block
+    (the preprocessing input): points in the sensor frame, sensor at the origin."""
+    scene_rng, traj_rng, noise_rng = (np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(3))
+    s, x, y, yaw = _smooth_trajectory(traj_rng, 20.0)
+    lo, hi = _urban_scene(scene_rng, np.stack([x, y], axis=1))
+    i = len(s) // 2
+    pts = lidar_frame(noise_rng, yaw_pose(x[i], y[i], 1.8, yaw[i]), lo, hi, _lidar_dirs(n_rings, n_az, elev))
+    return pts, np.zeros(3)
+
+
+def thin_wall_pair(seed=1, thickness=0.1, noise=0.01):
+    """Two raw 64-ring frames on opposite sides of a thin partition wall.
+
+    A 20 x 20 m room (3 m perimeter walls), a partition 5 m long, `thickness`
+    thick and 2.5 m high whose faces lie inside one voxel of 0.25/0.5/1 m
+    (centre plane y = 0.35 m), and ten 2-3 m boxes away from the partition.
+    Sensor A (the target) sits 2 m south of the partition, sensor B (the
+    source) 2.5 m north, both at 1.2 m height; each sees only its own face of
+    the partition.  Returns (points_A, points_B) in their sensor frames, the
+    relative pose T_A^-1 T_B and the sensors' world poses.
+    """
+    scene_rng, noise_rng = (np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(2))
+    W, th, H = 10.0, 0.3, 3.0
+    lo = [[-W - th, -W - th, 0], [W, -W - th, 0], [-W - th, -W - th, 0], [-W - th, W, 0],
+          [-2.5, 0.35 - thickness / 2, 0]]
+    hi = [[-W, W + th, H], [W + th, W + th, H], [W + th, -W, H], [W + th, W + th, H],
+          [2.5, 0.35 + thickness / 2, 2.5]]
+    for _ in range(10):
+        c = scene_rng.uniform(-8, 8, 2)
+        while abs(c[1]) < 4.5 and abs(c[0]) < 4.5:
+            c = scene_rng.uniform(-8, 8, 2)
+        sz = scene_rng.uniform(2.0, 3.0, 2)
+        h = scene_rng.uniform(0.5, 2.5)
+        lo.append([c[0] - sz[0] / 2, c[1] - sz[1] / 2, 0])
+        hi.append([c[0] + sz[0] / 2, c[1] + sz[1] / 2, h])
+    lo, hi = np.array(lo, float), np.array(hi, float)
+    dirs = _lidar_dirs(64, 1024, (-30.0, 30.0))
+    TA = yaw_pose(0.0, -2.0, 1.2, 0.3)
+    TB = yaw_pose(0.5, 2.5, 1.2, -0.4)
+    pa = lidar_frame(noise_rng, TA, lo, hi, dirs, rmin=0.5, rmax=40.0, noise=noise)
+    pb = lidar_frame(noise_rng, TB, lo, hi, dirs, rmin=0.5, rmax=40.0, noise=noise)
+    return {"target_raw": pa, "source_raw": pb, "T_true": inv_pose(TA) @ TB, "T_A": TA, "T_B": TB,
+            "wall": (lo[4], hi[4])}
+
+
+def local_mapping(seed=8, n_frames=15, spacing=1.0, n_rings=64, n_az=1024, angle_deg=0.5, trans_m=0.05):
+    """Local-mapping submap (Sec. V-A): n_frames raw 64-ring frames along a
+    trajectory in the urban block, `spacing` metres apart, matched all-to-all:
+    one factor per pair i < j (source frame i into target frame j), 105 for 15
+    frames.  Frame poses are estimates = truth (x) a seeded (angle_deg,
+    trans_m) error per frame.  Raw points are in each sensor frame (the
+    preprocessing input); the sensor sits at each frame's origin."""
+    scene_rng, traj_rng, noise_rng, pose_rng = (np.random.default_rng(s) for s in
+                                                np.random.SeedSequence(seed).spawn(4))
+    s, x, y, yaw = _smooth_trajectory(traj_rng, float((n_frames - 1) * spacing))
+    lo, hi = _urban_scene(scene_rng, np.stack([x, y], axis=1))
+    dirs = _lidar_dirs(n_rings, n_az, (-22.5, 22.5))
+    truth, est, raw = [], [], []
+    for f in range(n_frames):
+        i = int(round(f * spacing / (s[1] - s[0])))
+        T = yaw_pose(x[i], y[i], 1.8, yaw[i])
+        truth.append(T)
+        est.append(T @ random_pose(pose_rng, angle_deg, trans_m))
+        raw.append(lidar_frame(noise_rng, T, lo, hi, dirs))
+    pairs = [(i, j) for i in range(n_frames) for j in range(i + 1, n_frames)]
+    return {"raw": raw, "poses_true": truth, "poses_est": est, "pairs": pairs,
+            "rel_est": [inv_pose(est[j]) @ est[i] for (i, j) in pairs],
+            "rel_true": [inv_pose(truth[j]) @ truth[i] for (i, j) in pairs]}
+
+
+def config2(seed=2, n_keyframes=20, resolutions=(0.25, 0.5, 1.0, 2.0), n_rings=32, n_az=1000,
+            workers=-1):
+    """One new 32-ring frame matched against 20 keyframes spaced 1 m apart (4-level maps)."""
+    scene_rng, traj_rng, noise_rng, pose_rng = (np.random.default_rng(s) for s in
+                                                np.random.SeedSequence(seed).spawn(4))
+    s, x, y, yaw = _smooth_trajectory(traj_rng, float(n_keyframes))
+    lo, hi = _urban_scene(scene_rng, np.stack([x, y], axis=1))
     dirs = _lidar_dirs(n_rings, n_az)
     poses = []
     for k in range(n_keyframes + 1):

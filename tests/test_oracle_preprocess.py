@@ -114,3 +114,15 @@ def test_rigid_motion_equivariance(seed):
     _, n1, _ = pp.regularize(C, P, sensor)
     _, n2, _ = pp.regularize(C2, P @ q.T + t, q @ sensor + t)
     np.testing.assert_allclose(n2, n1 @ q.T, atol=1e-8)
+
+
+def test_knn_tree_equals_brute_force():
+    rng = np.random.default_rng(6)
+    P = rng.normal(size=(900, 3)) * [5.0, 5.0, 0.5]
+    a_idx, a_d2 = pp.knn(P, 12)
+    b_idx, b_d2 = pp.knn_tree(P, 12)
+    np.testing.assert_array_equal(a_idx, b_idx)
+    np.testing.assert_array_equal(a_d2, b_d2)
+    a_idx, _ = pp.knn(P[:5], 8)
+    b_idx, _ = pp.knn_tree(P[:5], 8)
+    np.testing.assert_array_equal(a_idx, b_idx)

@@ -176,8 +176,8 @@ def measured_traffic(path, launch):
     try:
         if p.get("kernel_sources_sha256") != kernel_sources_sha256():
             return None
-        if p.get("launch") != "block %d tile %d grid %d" % (launch["block_threads"], launch["tile_points"],
-                                                           launch["grid_blocks"]):
+        if p.get("launch") != "block %d tile %d grid %d order %d" % (
+                launch["block_threads"], launch["tile_points"], launch["grid_blocks"], launch["tile_order"]):
             return None
         return float(p["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -189,7 +189,7 @@ def _csvs(d, suffix):
     return sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
 
 
-def summarize_profiles(kt_dir, fetch_dir, write_dir, command, tile_points, workload, warmup):
+def summarize_profiles(kt_dir, fetch_dir, write_dir, command, tile_points, tile_order, workload, warmup):
     """Text summary of one rocprofv3 kernel-trace run and two counter runs
     (FETCH_SIZE, WRITE_SIZE) of ``bench.py --profile-steps``.  The counters are
     scaled by what they read for the calibration kernels of known size that the
@@ -255,7 +255,7 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, command, tile_points, workl
     ] + ["#   " + c for c in command] + [
         "#",
         "kernel: %s" % tile["Name"].split("(")[0],
-        "launch: block %d tile %d grid %d" % (block, tile_points, grid),
+        "launch: block %d tile %d grid %d order %d" % (block, tile_points, grid, tile_order),
         "kernel_sources_sha256: %s" % kernel_sources_sha256(),
         "tile_kernel_calls: %s" % tile["Calls"],
         "tile_kernel_avg_ns: %.0f" % float(tile["AverageNs"]),
@@ -327,6 +327,8 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: library default / tuned)")
     ap.add_argument("--tile", type=int, default=0, help="source points per tile (0: default / tuned)")
     ap.add_argument("--bpc", type=int, default=0, help="persistent workgroups per CU (0: default / tuned)")
+    ap.add_argument("--tile-order", type=int, default=0,
+                    help="1: contiguous tile range per XCD, 2: tiles dealt round-robin to XCDs (0: default / tuned)")
     ap.add_argument("--lane-kahan", action="store_true", help="Kahan-compensated FP32 sums inside each lane")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -338,8 +340,8 @@ def main():
     args = ap.parse_args()
     if args.summarize_profiles:
         tag = "global submap batch, %d submaps" % args.submaps if args.workload == "global" else args.workload
-        sys.stdout.write(summarize_profiles(*args.summarize_profiles, args.profile_command, args.tile, tag,
-                                            args.warmup))
+        sys.stdout.write(summarize_profiles(*args.summarize_profiles, args.profile_command, args.tile,
+                                            args.tile_order or 1, tag, args.warmup))
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)"
@@ -355,7 +357,7 @@ def main():
     cfg, desc = make_workload(args.workload, args.submaps)
     ctx = vgicp.Context(0)
     t = time.time()
-    shape = {"block": args.block, "tile": args.tile, "blocks_per_cu": args.bpc}
+    shape = {"block": args.block, "tile": args.tile, "blocks_per_cu": args.bpc, "tile_order": args.tile_order}
     maps, srcs, batch = vgicp.build_workload(ctx, cfg, precision=args.precision, use_graph=True,
                                              lane_kahan=args.lane_kahan, **shape)
     torch.cuda.synchronize()
@@ -400,7 +402,8 @@ def main():
     plain_rate = None
     if args.plain_steps > 0:
         _, _, plain = vgicp.build_workload(ctx, cfg, precision=args.precision, use_graph=False, plain=True,
-                                           block=info["block_threads"], tile=info["tile_points"])
+                                           block=info["block_threads"], tile=info["tile_points"],
+                                           tile_order=info["tile_order"])
         plain.linearize(poses)
         t0 = time.perf_counter()
         for _ in range(args.plain_steps):

@@ -95,6 +95,10 @@ typedef struct {
                                    inside each lane (sums above a lane are FP64 either way) */
     const char* tune_cache;     /* NULL: no autotuning.  Otherwise a file path: tuned shapes
                                    are read from it, or measured and appended to it */
+    int32_t tile_order;         /* order in which the persistent grid takes tiles: 0 default
+                                   (1), 1 = eight contiguous ranges, one per XCD, 2 = tiles
+                                   dealt round-robin to the eight XCDs (all XCDs work in
+                                   the same window of factors); results are identical */
 } vg_batch_options;
 
 /* ---- context ---------------------------------------------------------- */
@@ -198,9 +202,11 @@ vg_status vg_create_factor_batch(vg_context* ctx, int64_t F, vg_source* const* s
                                  vg_voxelmap* const* tgt, const double* target_viewpoints,
                                  const vg_batch_options* opts, vg_batch** out);
 /* Shape of a batch: total source points, number of work tiles, and the launch
- * shape in use (block threads, tile points, persistent workgroups). */
+ * shape in use (block threads, tile points, persistent workgroups, tile order).
+ * Any output may be NULL. */
 vg_status vg_batch_info(const vg_batch* batch, int64_t* total_points, int64_t* n_tiles,
-                        int32_t* block_threads, int32_t* tile_points, int32_t* grid_blocks);
+                        int32_t* block_threads, int32_t* tile_points, int32_t* grid_blocks,
+                        int32_t* tile_order);
 vg_status vg_batch_destroy(vg_batch* batch);
 
 /* Linearize every factor at its pose (host arrays): poses F x 12 in; e F,
@@ -264,7 +270,8 @@ vg_status vg_correspondences(vg_batch* batch, const double* pose, int64_t factor
  * choice is stable under timing noise) and, when the batch was created with a
  * tune_cache path, appended to that file under a key made of the device name
  * and the batch signature (precision, F, total points, levels, validation).
- * chosen (may be NULL) receives {block_threads, tile_points, blocks_per_cu}. */
+ * chosen (may be NULL) receives {block_threads, tile_points, blocks_per_cu,
+ * tile_order}.  Both tile orders are candidates. */
 vg_status vg_batch_tune(vg_batch* batch, const double* poses, int32_t reps, int32_t* chosen);
 
 /* ---- pose graphs: two-node expansion and normal-equation assembly ------- */

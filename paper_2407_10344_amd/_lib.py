@@ -51,6 +51,7 @@ class BatchOptions(C.Structure):
         ("blocks_per_cu", C.c_int32),
         ("lane_kahan", C.c_int32),
         ("tune_cache", C.c_char_p),
+        ("tile_order", C.c_int32),
     ]
 
 
@@ -76,7 +77,7 @@ SIGNATURES = {
     "vg_build_voxelmap_from_cloud": (C.c_int, [P, P, P, I32, P]),
     "vg_cloud_destroy": (C.c_int, [P]),
     "vg_create_factor_batch": (C.c_int, [P, I64, P, P, P, P, P]),
-    "vg_batch_info": (C.c_int, [P, P, P, P, P, P]),
+    "vg_batch_info": (C.c_int, [P, P, P, P, P, P, P]),
     "vg_batch_destroy": (C.c_int, [P]),
     "vg_linearize": (C.c_int, [P, P, P, P, P, P]),
     "vg_evaluate": (C.c_int, [P, P, P]),

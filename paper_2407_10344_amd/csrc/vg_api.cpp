@@ -635,7 +635,7 @@ std::string tune_key(const vg_batch* b) {
     return k.str();
 }
 
-bool tune_lookup(const vg_batch* b, int* block, int* tile, int* bpc) {
+bool tune_lookup(const vg_batch* b, int* block, int* tile, int* bpc, int* order) {
     if (b->opt.tune_cache == nullptr) return false;
     std::ifstream in(b->opt.tune_cache);
     if (!in) return false;
@@ -644,15 +644,17 @@ bool tune_lookup(const vg_batch* b, int* block, int* tile, int* bpc) {
     bool found = false;
     while (std::getline(in, line)) {
         if (line.find(key) == std::string::npos) continue;
-        int bl = 0, tp = 0, bc = 0;
+        int bl = 0, tp = 0, bc = 0, to = 0;
         const char* p1 = std::strstr(line.c_str(), "\"block\": ");
         const char* p2 = std::strstr(line.c_str(), "\"tile_points\": ");
         const char* p3 = std::strstr(line.c_str(), "\"blocks_per_cu\": ");
-        if (p1 && p2 && p3 && std::sscanf(p1 + 9, "%d", &bl) == 1 && std::sscanf(p2 + 15, "%d", &tp) == 1 &&
-            std::sscanf(p3 + 17, "%d", &bc) == 1) {
+        const char* p4 = std::strstr(line.c_str(), "\"tile_order\": ");
+        if (p1 && p2 && p3 && p4 && std::sscanf(p1 + 9, "%d", &bl) == 1 && std::sscanf(p2 + 15, "%d", &tp) == 1 &&
+            std::sscanf(p3 + 17, "%d", &bc) == 1 && std::sscanf(p4 + 14, "%d", &to) == 1) {
             *block = bl;
             *tile = tp;
             *bpc = bc;
+            *order = to;
             found = true;   // last entry wins
         }
     }
@@ -795,6 +797,7 @@ extern "C" vg_status vg_create_factor_batch(vg_context* ctx, int64_t F, vg_sourc
     int tile = o.tile_points ? o.tile_points : 2048;
     int bpc = o.blocks_per_cu ? o.blocks_per_cu : default_blocks_per_cu(block);
     if (!valid_shape(block, tile, bpc)) return invalid("invalid launch shape (block 64/128/256/512, tile a multiple of 64 up to 8192)");
+    if (o.tile_order < 0 || o.tile_order > 2) return invalid("tile_order must be 0, 1 or 2");
     VG_HIP(hipSetDevice(ctx->device));
     auto* b = new vg_batch();
     b->ctx = ctx;
@@ -827,14 +830,16 @@ extern "C" vg_status vg_create_factor_batch(vg_context* ctx, int64_t F, vg_sourc
     b->block = block;
     b->tile_points = tile;
     b->blocks_per_cu = bpc;
+    b->tile_order = o.tile_order ? o.tile_order : 1;
     if (opts && opts->tune_cache) {
         b->opt.tune_cache = strdup(opts->tune_cache);
-        int bl = 0, tp = 0, bc = 0;
-        if (!o.block_threads && !o.tile_points && !o.blocks_per_cu && tune_lookup(b, &bl, &tp, &bc) &&
-            valid_shape(bl, tp, bc)) {
+        int bl = 0, tp = 0, bc = 0, to = 0;
+        if (!o.block_threads && !o.tile_points && !o.blocks_per_cu && !o.tile_order &&
+            tune_lookup(b, &bl, &tp, &bc, &to) && valid_shape(bl, tp, bc) && (to == 1 || to == 2)) {
             b->block = bl;
             b->tile_points = tp;
             b->blocks_per_cu = bc;
+            b->tile_order = to;
         }
     }
     build_tiles(b);
@@ -876,7 +881,7 @@ extern "C" vg_status vg_create_factor_batch(vg_context* ctx, int64_t F, vg_sourc
 }
 
 extern "C" vg_status vg_batch_info(const vg_batch* b, int64_t* total_points, int64_t* n_tiles, int32_t* block_threads,
-                                   int32_t* tile_points, int32_t* grid_blocks) {
+                                   int32_t* tile_points, int32_t* grid_blocks, int32_t* tile_order) {
     g_err.clear();
     if (!bat_ok(b)) return state_err("invalid batch");
     if (total_points) *total_points = b->total_points;
@@ -884,6 +889,7 @@ extern "C" vg_status vg_batch_info(const vg_batch* b, int64_t* total_points, int
     if (block_threads) *block_threads = b->block;
     if (tile_points) *tile_points = b->tile_points;
     if (grid_blocks) *grid_blocks = b->grid;
+    if (tile_order) *tile_order = b->tile_order;
     return VG_OK;
 }
 
@@ -1161,31 +1167,36 @@ extern "C" vg_status vg_batch_tune(vg_batch* b, const double* poses, int32_t rep
     VG_HIP(hipMemcpyAsync(b->d_poses, b->h_poses, sizeof(double) * 12 * b->F, hipMemcpyHostToDevice, st));
     // candidates in order of preference: a later candidate replaces an earlier one
     // only when it is faster by more than 1.5 %, so timing noise does not flip the choice
+    const int orders[] = {1, 2};
     const int tiles[] = {8192, 4096, 2048, 1024};
     const int blocks[] = {256, 128, 512};
     const int occ[] = {2, 1, 4};   // multiples of the full-occupancy workgroup count
     float best = 1e30f;
-    int bb = b->block, bt = b->tile_points, bc = b->blocks_per_cu;
+    int bb = b->block, bt = b->tile_points, bc = b->blocks_per_cu, bo = b->tile_order;
     for (int tp : tiles) {
         b->tile_points = tp;
         build_tiles(b);
         VG_TRY(upload_schedule(b));
-        for (int bl : blocks)
-            for (int oc : occ) {
-                b->block = bl;
-                b->blocks_per_cu = std::max(1, oc * 1024 / bl);
-                b->grid = (int)std::max<int64_t>(
-                    1, std::min<int64_t>((int64_t)b->ctx->num_cu * b->blocks_per_cu, (int64_t)b->h_tiles.size()));
-                float t1 = 0.f, t2 = 0.f;
-                VG_TRY(time_device(b, reps, &t1, &t2));
-                if (t1 + t2 < best * 0.985f) {
-                    best = t1 + t2;
-                    bb = bl;
-                    bt = tp;
-                    bc = b->blocks_per_cu;
+        for (int to : orders)
+            for (int bl : blocks)
+                for (int oc : occ) {
+                    b->tile_order = to;
+                    b->block = bl;
+                    b->blocks_per_cu = std::max(1, oc * 1024 / bl);
+                    b->grid = (int)std::max<int64_t>(
+                        1, std::min<int64_t>((int64_t)b->ctx->num_cu * b->blocks_per_cu, (int64_t)b->h_tiles.size()));
+                    float t1 = 0.f, t2 = 0.f;
+                    VG_TRY(time_device(b, reps, &t1, &t2));
+                    if (t1 + t2 < best * 0.985f) {
+                        best = t1 + t2;
+                        bb = bl;
+                        bt = tp;
+                        bc = b->blocks_per_cu;
+                        bo = to;
+                    }
                 }
-            }
     }
+    b->tile_order = bo;
     b->block = bb;
     b->tile_points = bt;
     b->blocks_per_cu = bc;
@@ -1195,12 +1206,13 @@ extern "C" vg_status vg_batch_tune(vg_batch* b, const double* poses, int32_t rep
         chosen[0] = bb;
         chosen[1] = bt;
         chosen[2] = bc;
+        chosen[3] = bo;
     }
     if (b->opt.tune_cache) {
         std::ofstream outf(b->opt.tune_cache, std::ios::app);
         if (outf) {
             outf << "{\"key\": \"" << tune_key(b) << "\", \"block\": " << bb << ", \"tile_points\": " << bt
-                 << ", \"blocks_per_cu\": " << bc << ", \"ms\": " << best << "}\n";
+                 << ", \"blocks_per_cu\": " << bc << ", \"tile_order\": " << bo << ", \"ms\": " << best << "}\n";
         }
     }
     return VG_OK;

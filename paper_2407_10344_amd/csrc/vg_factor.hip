@@ -196,7 +196,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
     const FactorDesc* __restrict__ fac, const Tile* __restrict__ tiles, int32_t t_begin, int32_t t_end,
     const double* __restrict__ poses, const float* __restrict__ posef, double* __restrict__ partials,
     uint32_t* __restrict__ counter, int32_t validate, const double* __restrict__ grad_e,
-    void* __restrict__ grad_points, int32_t points_dtype) {
+    void* __restrict__ grad_points, int32_t points_dtype, int32_t interleave) {
     using T = typename PT<PREC>::T;
     constexpr int NW = BLOCK / 64;
     constexpr bool KAHAN = KH && (PREC == kC32);
@@ -206,12 +206,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
     __shared__ int32_t s_tile;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    // XCD-aware work distribution: the tile range is cut into kParts contiguous
-    // partitions with one counter each; workgroups are dispatched round-robin
-    // over the XCDs, so workgroup b starts on partition b % kParts and its XCD's
-    // L2 serves a narrow window of factors (which share sources and targets).
-    // A workgroup whose partition is exhausted moves on to the next one.
-    const int32_t span = (t_end - t_begin + kParts - 1) / kParts;
+    // XCD-aware work distribution: the tiles are split into kParts partitions with
+    // one counter each; workgroups are dispatched round-robin over the XCDs, so
+    // workgroup b starts on partition b % kParts, i.e. on its XCD's partition.
+    // Contiguous partitions give each XCD's L2 a narrow window of factors (which
+    // share sources and targets); interleaved partitions (tile i in partition
+    // i % kParts) keep all XCDs in one window, so the last-level cache holds a
+    // single working set.  A workgroup whose partition is exhausted moves on to
+    // the next one.
+    const int32_t ntiles = t_end - t_begin;
+    const int32_t span = (ntiles + kParts - 1) / kParts;
     int part = (int)(blockIdx.x % kParts);
     int tried = 0;
 
@@ -219,13 +223,24 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
         if (threadIdx.x == 0) {
             int32_t take = -1;
             while (tried < kParts) {
-                const int32_t lo = t_begin + part * span;
-                const int32_t hi = min(lo + span, t_end);
-                if (lo < hi) {
-                    const uint32_t k = atomicAdd(counter + part, 1u);
-                    if (k < (uint32_t)(hi - lo)) {
-                        take = lo + (int32_t)k;
-                        break;
+                if (interleave) {
+                    const int32_t cnt = ntiles > part ? (ntiles - part + kParts - 1) / kParts : 0;
+                    if (cnt > 0) {
+                        const uint32_t k = atomicAdd(counter + part, 1u);
+                        if (k < (uint32_t)cnt) {
+                            take = t_begin + part + kParts * (int32_t)k;
+                            break;
+                        }
+                    }
+                } else {
+                    const int32_t lo = t_begin + part * span;
+                    const int32_t hi = min(lo + span, t_end);
+                    if (lo < hi) {
+                        const uint32_t k = atomicAdd(counter + part, 1u);
+                        if (k < (uint32_t)(hi - lo)) {
+                            take = lo + (int32_t)k;
+                            break;
+                        }
                     }
                 }
                 part = (part + 1) % kParts;
@@ -789,7 +804,7 @@ static vg_status launch_tiles_t(vg_batch* b, const double* d_poses, int32_t t0, 
 #define VG_LAUNCH(BS)                                                                                         \
     k_tiles<MODE, PREC, BS, KH><<<grid, BS, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, b->d_posef,        \
                                                      b->d_partials, b->d_counter, v, d_grad_e, d_grad_points,  \
-                                                     points_dtype)
+                                                     points_dtype, b->tile_order == 2 ? 1 : 0)
     switch (b->block) {
         case 64: VG_LAUNCH(64); break;
         case 128: VG_LAUNCH(128); break;

@@ -166,6 +166,7 @@ struct vg_batch {
     int64_t total_points = 0;
     int64_t grad_rows = 0;               // rows of the concatenated point gradient
     int block = 256, tile_points = 2048, grid = 0, blocks_per_cu = 0;
+    int tile_order = 1;                  // 1 contiguous per XCD, 2 round-robin over XCDs
     // device buffers
     vg::FactorDesc* d_fac = nullptr;
     vg::Tile* d_tiles = nullptr;

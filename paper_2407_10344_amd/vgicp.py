@@ -214,7 +214,7 @@ class FactorBatch:
 
     def __init__(self, ctx: Context, sources, maps, viewpoints=None, precision="fp32c", validation=False,
                  use_graph=True, plain=False, block=0, tile=0, blocks_per_cu=0, lane_kahan=False,
-                 tune_cache=None):
+                 tune_cache=None, tile_order=0):
         lib = load()
         self.ctx = ctx
         self.sources = list(sources)
@@ -234,6 +234,7 @@ class FactorBatch:
         o.blocks_per_cu = int(blocks_per_cu)
         o.lane_kahan = int(bool(lane_kahan))
         o.tune_cache = tune_cache.encode() if tune_cache else None
+        o.tile_order = int(tile_order)
         srcs = (C.c_void_p * F)(*[s.handle.value for s in self.sources])
         tgts = (C.c_void_p * F)(*[m.handle.value for m in self.maps])
         vp = None if viewpoints is None else _f64(viewpoints, (F, 3))
@@ -250,10 +251,11 @@ class FactorBatch:
 
     def info(self):
         tp, nt = C.c_int64(), C.c_int64()
-        bl, ti, gr = C.c_int32(), C.c_int32(), C.c_int32()
-        check(load().vg_batch_info(self.handle, C.byref(tp), C.byref(nt), C.byref(bl), C.byref(ti), C.byref(gr)))
+        bl, ti, gr, to = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        check(load().vg_batch_info(self.handle, C.byref(tp), C.byref(nt), C.byref(bl), C.byref(ti), C.byref(gr),
+                                   C.byref(to)))
         return {"total_points": tp.value, "n_tiles": nt.value, "block_threads": bl.value,
-                "tile_points": ti.value, "grid_blocks": gr.value}
+                "tile_points": ti.value, "grid_blocks": gr.value, "tile_order": to.value}
 
     def linearize(self, poses):
         P = poses12(poses)
@@ -329,9 +331,10 @@ class FactorBatch:
 
     def tune(self, poses, reps=3):
         P = poses12(poses)
-        ch = np.zeros(3, dtype=np.int32)
+        ch = np.zeros(4, dtype=np.int32)
         check(load().vg_batch_tune(self.handle, _p(P), int(reps), _p(ch)))
-        return {"block_threads": int(ch[0]), "tile_points": int(ch[1]), "blocks_per_cu": int(ch[2])}
+        return {"block_threads": int(ch[0]), "tile_points": int(ch[1]), "blocks_per_cu": int(ch[2]),
+                "tile_order": int(ch[3])}
 
     def time_kernels(self, poses, reps=10):
         P = poses12(poses)

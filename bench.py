@@ -286,6 +286,23 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, command, tile_points, tile_
     return "\n".join(lines) + "\n"
 
 
+def summarize_counters(dirs, command):
+    """Mean per dispatch of each counter of the tile kernel k_tiles<lin, fp32c>."""
+    import csv
+    from collections import defaultdict
+    agg = defaultdict(list)
+    for d in dirs:
+        for f in _csvs(d, "_counter_collection.csv"):
+            for r in csv.DictReader(open(f)):
+                if r["Kernel_Name"].startswith("void vg::k_tiles<0, 0,"):
+                    agg[r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = ["# rocprofv3 counters of the tile kernel k_tiles<lin, fp32c> (mean per dispatch)", "#"]
+    lines += ["#   " + c for c in command] + ["#"]
+    for k in sorted(agg):
+        lines.append("%s: %.6e (%d dispatches)" % (k, sum(agg[k]) / len(agg[k]), len(agg[k])))
+    return "\n".join(lines) + "\n"
+
+
 def bench_preprocess(args, r=0.25, k=10):
     """Frame preprocessing: one raw 128-ring frame (host FP64) -> downsampled cloud
     with k-NN, covariances and normals on the device; a step is one frame."""
@@ -314,12 +331,78 @@ def bench_preprocess(args, r=0.25, k=10):
     ctx.close()
 
 
+def bench_local(args, r=0.25, k=10, res=(0.25, 0.5, 1.0)):
+    """Local-mapping batch: 15 raw frames preprocessed on the device, 105
+    all-to-all factors with surface validation; a step is one linearization of
+    the batch (poses resident, one upload / download)."""
+    import torch
+    import synth
+    from paper_2407_10344_amd import vgicp
+    d = synth.local_mapping()
+    ctx = vgicp.Context(0)
+    t0 = time.perf_counter()
+    clouds = [vgicp.Cloud(ctx, p, r, k, np.zeros(3)) for p in d["raw"]]
+    srcs = [vgicp.Source.from_cloud(ctx, c) for c in clouds]
+    maps = [vgicp.VoxelMap.from_cloud(ctx, c, list(res)) for c in clouds]
+    torch.cuda.synchronize()
+    prep_ms = (time.perf_counter() - t0) * 1e3 / len(clouds)
+    pairs = d["pairs"]
+    shape = {"block": args.block, "tile": args.tile, "blocks_per_cu": args.bpc, "tile_order": args.tile_order}
+    batch = vgicp.FactorBatch(ctx, [srcs[i] for i, _ in pairs], [maps[j] for _, j in pairs],
+                              viewpoints=np.zeros((len(pairs), 3)), precision=args.precision, validation=True,
+                              use_graph=True, lane_kahan=args.lane_kahan, **shape)
+    poses = vgicp.poses12(np.array(d["rel_est"]))
+    if not args.no_tune and not any(shape.values()):
+        batch.tune(poses, reps=3)
+    info = batch.info()
+    for _ in range(args.warmup):
+        e, H, b, inl = batch.linearize(poses)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e, H, b, inl = batch.linearize(poses)
+    dt = (time.perf_counter() - t0) / args.steps
+    pts = sum(c.n for c in (clouds[i] for i, _ in pairs))
+    hits = int(inl.sum())
+    L = inl.shape[1]
+    B_alg = pts * B_POINT + pts * L * B_KEY + hits * B_HIT + len(pairs) * B_FACTOR
+    tk = batch.time_kernels(poses, reps=20)
+    plain = vgicp.FactorBatch(ctx, [srcs[i] for i, _ in pairs], [maps[j] for _, j in pairs],
+                              viewpoints=np.zeros((len(pairs), 3)), precision=args.precision, validation=True,
+                              use_graph=False, plain=True, block=info["block_threads"], tile=info["tile_points"])
+    plain.linearize(poses)
+    t0 = time.perf_counter()
+    for _ in range(5):
+        plain.linearize(poses)
+    plain_dt = (time.perf_counter() - t0) / 5
+    plain.close()
+    out = {"metric": "source points linearized/sec (e,H,b), batched vs plain, at rel. err <=1e-5",
+           "value": pts / dt, "unit": "source points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"fp32c": "f32", "fp32": "f32", "fp64": "f64"}[args.precision], "data": "synthetic",
+           "config": {"workload": "local-mapping batch", "frames": len(clouds), "factors": len(pairs),
+                      "voxel_m": list(res), "levels": L, "surface_validation": True, "precision": args.precision,
+                      "total_source_points": pts, "inlier_pairs": hits, "launch": info,
+                      "preprocess_ms_per_frame": prep_ms},
+           "plain": {"value": pts / plain_dt, "unit": "source points/s", "batched_speedup": plain_dt / dt},
+           "roofline": {"bound": "hbm", "achieved": B_alg / (tk["tile_kernel_ms"] * 1e-3) / 1e9,
+                        "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                        "frac": B_alg / (tk["tile_kernel_ms"] * 1e-3) / HBM_PEAK, "traffic": None,
+                        "kernel_ms": tk["tile_kernel_ms"], "reduce_ms": tk["reduce_ms"], "call_ms": tk["call_ms"],
+                        "algorithmic_bytes": B_alg}}
+    print(json.dumps(out), flush=True)
+    batch.close()
+    for x in srcs + maps + clouds:
+        x.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="global", choices=["global", "odometry", "single", "preprocess"])
+    ap.add_argument("--workload", default="global", choices=["global", "odometry", "single", "preprocess", "local"])
     ap.add_argument("--submaps", type=int, default=500)
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp64"])
     ap.add_argument("--plain-steps", type=int, default=2)
@@ -337,7 +420,12 @@ def main():
                     help="write the text summary of three rocprofv3 runs of --profile-steps and exit")
     ap.add_argument("--profile-command", action="append", default=[],
                     help="command line recorded in the summary (repeatable)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_DIR",
+                    help="print the mean per dispatch of every counter of the tile kernel in rocprofv3 --pmc runs")
     args = ap.parse_args()
+    if args.summarize_counters:
+        sys.stdout.write(summarize_counters(args.summarize_counters, args.profile_command))
+        return
     if args.summarize_profiles:
         tag = "global submap batch, %d submaps" % args.submaps if args.workload == "global" else args.workload
         sys.stdout.write(summarize_profiles(*args.summarize_profiles, args.profile_command, args.tile,
@@ -353,6 +441,9 @@ def main():
 
     if args.workload == "preprocess":
         bench_preprocess(args)
+        return
+    if args.workload == "local":
+        bench_local(args)
         return
     cfg, desc = make_workload(args.workload, args.submaps)
     ctx = vgicp.Context(0)

@@ -20,6 +20,11 @@ BUILD = os.path.join(PKG, "_build")
 
 SOURCES = ["vg_api.cpp", "vg_voxelmap.hip", "vg_factor.hip", "vg_lm.hip", "vg_graph.hip", "vg_preprocess.hip"]
 
+# per-source flags: the preprocessing file forms squared distances that decide
+# neighbour ranks with each operation rounded on its own, so nothing there may
+# be contracted into fused multiply-adds
+SOURCE_FLAGS = {"vg_preprocess.hip": ["-ffp-contract=off"]}
+
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 FLAGS = [
@@ -43,9 +48,11 @@ FLAGS = [
 
 def _compile(src: str, extra=()) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    flags = [f for f in FLAGS if not (f.startswith("-ffp-contract") and src in SOURCE_FLAGS)]
+    flags += SOURCE_FLAGS.get(src, [])
+    cmd = [HIPCC, *flags, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [HIPCC, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *flags, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr[-8000:]))

@@ -146,9 +146,9 @@ __device__ __forceinline__ int32_t cell_find(const uint64_t* __restrict__ hkeys,
     }
 }
 
-// squared distance with every operation rounded on its own (no contraction)
+// squared distance with every operation rounded on its own: this file is
+// compiled with -ffp-contract=off, so no multiply-add is fused
 __device__ __forceinline__ double sqdist_rn(double ax, double ay, double az, double bx, double by, double bz) {
-#pragma clang fp contract(off)
     const double dx = bx - ax, dy = by - ay, dz = bz - az;
     const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
     return (xx + yy) + zz;

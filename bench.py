@@ -111,6 +111,14 @@ def cpu_baseline(cfg, batch_out, budget_s=10.0):
         results = {f: r for f, r in ex.map(run, cand) if r is not None}
     dt = time.perf_counter() - t0
     pts = sum(cfg["sources"][fac[f][0]].n for f in results)
+    # single-thread rate on the first factors of the same sample (about 3 s)
+    t1, pts1 = time.perf_counter(), 0
+    for f in cand:
+        factors[f].linearize(cfg["poses"][f])
+        pts1 += cfg["sources"][fac[f][0]].n
+        if time.perf_counter() - t1 > 3.0:
+            break
+    single = pts1 / (time.perf_counter() - t1)
     # parity of the device results on the same sample: relative errors e / H (Frobenius) / b.
     # Every factor above the tolerance, plus the 32 worst below it, is re-checked with the
     # face-band rule (a point within 1e-5 m of a voxel face may take either neighbouring
@@ -134,6 +142,7 @@ def cpu_baseline(cfg, batch_out, budget_s=10.0):
                        "max_after_face_band": mx(final),
                        "max_rechecked_after_face_band": mx({f: final[f] for f in recheck})})
     return {"value": pts / dt, "unit": "source points/s", "cores": cores, "kind": "oracle",
+            "single_thread_value": single,
             "sample": "%d of %d factors (%d source points) in %.1f s, FP64 C oracle, one factor per thread" % (
                 len(results), len(fac), pts, dt)}, parity
 

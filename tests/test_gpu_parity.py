@@ -279,7 +279,9 @@ def test_overlap_rate(vg, c2):
 def test_key_range_extremes(vg):
     """Voxels at the ends of the packable key range (|q - q0| up to 8191 / -8192 at
     0.5 m, i.e. ~4 km from the map origin) are found, and a query just outside the
-    range is a miss, not a wrap-around."""
+    range is a miss, not a wrap-around.  One map spans the whole range; each far
+    patch is matched by its own compact source (the compensated mode's lever arms
+    are taken from the source's own origin)."""
     vgicp, ctx = vg
     rng = np.random.default_rng(11)
     r = 0.5
@@ -291,36 +293,42 @@ def test_key_range_extremes(vg):
         return p, np.stack([C[:, 0, 0], C[:, 0, 1], C[:, 0, 2], C[:, 1, 1], C[:, 1, 2], C[:, 2, 2]], 1)
 
     centres = [(0.3, 0.3, 0.3), (8191 * r - 1.0, 0.0, 0.0), (0.0, -8192 * r + 1.0, 0.0), (0.0, 0.0, 8190 * r)]
-    pts, covs = zip(*[patch(c) for c in centres])
-    xyz = np.concatenate(pts)
-    cov = np.concatenate(covs)
-    keys = np.floor(xyz / r)
-    keep = np.all((keys >= -8192) & (keys <= 8191), axis=1)
-    xyz, cov = xyz[keep], cov[keep]
-    xyz[0] = [0.1, 0.1, 0.1]        # first point -> map origin 0, so relative keys = absolute keys
+    patches = []
+    for c in centres:
+        p, cv = patch(c)
+        keys = np.floor(p / r)
+        keep = np.all((keys >= -8192) & (keys <= 8191), axis=1)
+        patches.append((p[keep], cv[keep]))
+    patches[0][0][0] = [0.1, 0.1, 0.1]   # first point -> map origin 0, relative keys = absolute keys
+    xyz = np.concatenate([p for p, _ in patches])
+    cov = np.concatenate([cv for _, cv in patches])
     m = vgicp.VoxelMap(ctx, xyz, cov, [r])
-    src_xyz = xyz + rng.normal(scale=0.02, size=xyz.shape)
-    src = vgicp.Source(ctx, src_xyz, cov)
     ovm = oracle.VoxelMap(xyz, cov, [r])
-    of = oracle.Factor(src_xyz, cov, ovm)
     pose = np.eye(4)
     pose[:3, 3] = [0.01, -0.02, 0.005]
+    srcs, ofs = [], []
+    for p, cv in patches:
+        sp = p + rng.normal(scale=0.02, size=p.shape)
+        srcs.append(vgicp.Source(ctx, sp, cv))
+        ofs.append(oracle.Factor(sp, cv, ovm))
     for prec in ("fp32c", "fp64"):
-        batch = vgicp.FactorBatch(ctx, [src], [m], precision=prec)
-        e, H, b, inl = batch.linearize([pose])
-        assert inl[0, 0] == of.linearize(pose)["inliers"][0] > 0.9 * len(xyz)
-        check_factor(batch, 0, pose, of, e[0], H[0], b[0])
+        batch = vgicp.FactorBatch(ctx, srcs, [m] * len(srcs), precision=prec)
+        e, H, b, inl = batch.linearize([pose] * len(srcs))
+        for f, of in enumerate(ofs):
+            assert inl[f, 0] == of.linearize(pose)["inliers"][0] > 0.9 * of.n
+            check_factor(batch, f, pose, of, e[f], H[f], b[f])
         batch.close()
     # a query beyond +8191 on x finds nothing (no wrap-around to -8192)
     beyond = np.eye(4)
     beyond[0, 3] = 3.0
-    batch = vgicp.FactorBatch(ctx, [src], [m], precision="fp64")
+    batch = vgicp.FactorBatch(ctx, srcs[1:2], [m], precision="fp64")
     keys_d, found_d = batch.correspondences(beyond, 0)
-    tr = of.linearize(beyond, trace=True)
+    tr = ofs[1].linearize(beyond, trace=True)
     out_of_range = keys_d[:, 0, 0] > 8191
     assert out_of_range.any()
     assert np.all(found_d[out_of_range, 0] == 0)
     assert np.all(tr["vidx"][out_of_range, 0] == -1)
     batch.close()
-    src.close()
+    for s_ in srcs:
+        s_.close()
     m.close()

@@ -187,6 +187,7 @@ extern "C" vg_status vg_context_destroy(vg_context* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->ws) (void)hipFree(ctx->ws);
     ctx->magic = 0;
     delete ctx;
     return VG_OK;

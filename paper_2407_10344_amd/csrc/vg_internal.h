@@ -103,6 +103,8 @@ struct vg_context {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    void* ws = nullptr;          // grow-only device workspace of the preprocessing calls
+    size_t ws_bytes = 0;
     int num_cu = 0;
     std::string arch;
     std::string name;
@@ -148,6 +150,7 @@ struct vg_cloud {
     int32_t* counts = nullptr;  // m input points per voxel
     int32_t* nbr = nullptr;     // m x k
     double* d2 = nullptr;       // m x k
+    void* block = nullptr;      // one allocation holding every array above
     double first[3] = {0, 0, 0};// host copy of point 0 (origins of sources / maps made from the cloud)
     uint32_t magic = 0;
 };

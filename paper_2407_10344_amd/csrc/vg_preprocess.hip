@@ -5,12 +5,18 @@
 // Device pipeline:
 //   1. FP64 voxel keys -> stable radix sort of (key, point) -> run-length
 //      encoding; one thread per voxel sums its run in input order (FP64).
-//   2. k-NN on a uniform grid of cells of size h = 2 r: points sorted by cell,
-//      cells in an open-addressing table; one thread per query walks cubic
-//      shells of cells around its own cell and keeps the k best (distance,
-//      index) pairs in registers.  The walk stops once the k-th distance is
-//      below the distance to the unvisited region (strictly, with a 1e-9
-//      relative margin), so the result is exact.
+//   2. k-NN on a hierarchy of uniform grids (cells of 2r, 4r, ..., 64r):
+//      per grid, points sorted by cell and cells in an open-addressing table.
+//      One thread per query walks cubic shells of cells around its own cell
+//      (radius 0..1 cells) and keeps the k best (distance, index) pairs in
+//      registers, candidates read four at a time and rejected against the
+//      current k-th pair before any insertion work; the walk stops once the k-th distance is below the
+//      distance to the unvisited region (strictly, with a 1e-9 relative
+//      margin), so the result is exact.  A query that is not settled within
+//      two shells starts again on the next coarser grid (sparse regions: few
+//      large cells instead of many empty small ones); on the coarsest grid it
+//      walks on until settled, or scans every point once the next shell would
+//      hold more cells than the grid has occupied cells.
 //   3. one thread per point: mean and covariance of its neighbours (FP64),
 //      cyclic Jacobi eigen-decomposition, normal = smallest eigenvector,
 //      oriented towards the sensor, C = I - (1 - 1e-3) n n^T.
@@ -70,9 +76,7 @@ __global__ void k_ds_keys(const double* __restrict__ xyz, int64_t n, double r, u
 // point's grid cell for the neighbour search
 __global__ void k_ds_centroids(const double* __restrict__ xyz, const int32_t* __restrict__ sorted_idx,
                                const int32_t* __restrict__ offsets, const int32_t* __restrict__ counts, int64_t m,
-                               double h, double* __restrict__ out, int32_t* __restrict__ out_counts,
-                               uint64_t* __restrict__ cell_keys, int32_t* __restrict__ cell_idx,
-                               int32_t* __restrict__ box) {
+                               double* __restrict__ out, int32_t* __restrict__ out_counts) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= m) return;
     const int32_t o = offsets[v], c = counts[v];
@@ -88,16 +92,43 @@ __global__ void k_ds_centroids(const double* __restrict__ xyz, const int32_t* __
     out[3 * v + 1] = cy;
     out[3 * v + 2] = cz;
     out_counts[v] = c;
-    // |c / h| <= |c / r| / 2 < 2^19: always packable
-    const int64_t gx = (int64_t)floor(cx / h), gy = (int64_t)floor(cy / h), gz = (int64_t)floor(cz / h);
-    cell_keys[v] = pack21(gx, gy, gz);
-    cell_idx[v] = (int32_t)v;
-    atomicMin(&box[0], (int32_t)gx);
-    atomicMin(&box[1], (int32_t)gy);
-    atomicMin(&box[2], (int32_t)gz);
-    atomicMax(&box[3], (int32_t)gx);
-    atomicMax(&box[4], (int32_t)gy);
-    atomicMax(&box[5], (int32_t)gz);
+}
+
+// grid cell of every downsampled point (cell size h >= 2r: |c / h| < 2^19, always
+// packable) and the grid's cell bounding box
+__global__ void k_grid_keys(const double* __restrict__ c, int64_t m, double h, uint64_t* __restrict__ cell_keys,
+                            int32_t* __restrict__ cell_idx, int32_t* __restrict__ box) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    if (v < m) {
+        const int64_t gx = (int64_t)floor(c[3 * v] / h), gy = (int64_t)floor(c[3 * v + 1] / h),
+                      gz = (int64_t)floor(c[3 * v + 2] / h);
+        cell_keys[v] = pack21(gx, gy, gz);
+        cell_idx[v] = (int32_t)v;
+        lo[0] = hi[0] = (int32_t)gx;
+        lo[1] = hi[1] = (int32_t)gy;
+        lo[2] = hi[2] = (int32_t)gz;
+    }
+    // the wave's box first, then one atomic per wave and bound
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = min(lo[a], __shfl_xor(lo[a], w));
+            hi[a] = max(hi[a], __shfl_xor(hi[a], w));
+        }
+    if ((threadIdx.x & 63) == 0 && lo[0] <= hi[0]) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&box[a], lo[a]);
+            atomicMax(&box[3 + a], hi[a]);
+        }
+    }
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 __global__ void k_fill_u64p(uint64_t* p, int64_t n, uint64_t v) {
@@ -105,10 +136,10 @@ __global__ void k_fill_u64p(uint64_t* p, int64_t n, uint64_t v) {
     if (i < n) p[i] = v;
 }
 
-__global__ void k_cells_insert(const uint64_t* __restrict__ ucells, int64_t nc, uint64_t* __restrict__ hkeys,
-                               int32_t* __restrict__ hval, uint32_t lg) {
+__global__ void k_cells_insert(const uint64_t* __restrict__ ucells, const int32_t* __restrict__ nc,
+                               uint64_t* __restrict__ hkeys, int32_t* __restrict__ hval, uint32_t lg) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
+    if (c >= *nc) return;
     const uint64_t key = ucells[c];
     const uint32_t mask = (1u << lg) - 1;
     uint32_t s = cell_slot(key, lg);
@@ -159,111 +190,253 @@ __device__ __forceinline__ bool pair_less(double d, int32_t j, double D, int32_t
 }
 
 // Insert (d, j) into the list sorted by (distance, index) whose first kk slots
-// are live; every slot compares against the values before this insertion.
+// are live.  Precondition: (d, j) is below the pair at place kk - 1.  Walking
+// down from that place, each slot either takes its upper neighbour (the new
+// pair goes further up) or the new pair, once; every slot is written once,
+// after the slot below it has been read, so the update is in place.
 template <int KMAX>
 __device__ __forceinline__ void knn_insert(double (&D)[KMAX], int32_t (&I)[KMAX], int kk, double d, int32_t j) {
+    bool placed = false;
 #pragma unroll
     for (int s = KMAX - 1; s > 0; --s) {
-        if (s < kk) {
+        if (s < kk && !placed) {
             if (pair_less(d, j, D[s - 1], I[s - 1])) {
                 D[s] = D[s - 1];
                 I[s] = I[s - 1];
-            } else if (pair_less(d, j, D[s], I[s])) {
+            } else {
                 D[s] = d;
                 I[s] = j;
+                placed = true;
             }
         }
     }
-    if (pair_less(d, j, D[0], I[0])) {
+    if (!placed) {
         D[0] = d;
         I[0] = j;
     }
 }
 
-// Exact k-NN, one thread per query; queries are taken in cell order.  A query
-// whose next shell would hold more cells than 4 x (occupied cells) + 64 scans
-// every point instead (still exact, and bounded for very sparse clouds).
+// the pair at place kk - 1 (the k-th best so far)
 template <int KMAX>
-__global__ void __launch_bounds__(128) k_knn(const double* __restrict__ sx, const double* __restrict__ sy,
-                                             const double* __restrict__ sz, const int32_t* __restrict__ cidx,
-                                             const uint64_t* __restrict__ skeys, const int32_t* __restrict__ cstart,
-                                             const int32_t* __restrict__ ccount, const uint64_t* __restrict__ hkeys,
-                                             const int32_t* __restrict__ hval, uint32_t lg,
-                                             const int32_t* __restrict__ box, int64_t m, int64_t nc, int k, double h,
-                                             int32_t* __restrict__ nbr, double* __restrict__ nd2) {
+__device__ __forceinline__ void kth_pair(const double (&D)[KMAX], const int32_t (&I)[KMAX], int kk, double& wD,
+                                         int32_t& wI) {
+    wD = D[0];
+    wI = I[0];
+#pragma unroll
+    for (int s = 1; s < KMAX; ++s)
+        if (s == kk - 1) {
+            wD = D[s];
+            wI = I[s];
+        }
+}
+
+constexpr int kGrids = 6;       // cell sizes 2r, 4r, ..., 64r
+constexpr int kShells = 1;      // shells walked on every grid but the coarsest
+constexpr int kBudget = 1024;   // candidates a query may scan before it is handed to the wave-wide pass
+
+struct KnnGrid {
+    const double* sx;           // coordinates in cell order
+    const double* sy;
+    const double* sz;
+    const int32_t* cidx;        // cell order -> point index
+    const int32_t* cstart;      // per cell (cell ordinal)
+    const int32_t* ccount;
+    const uint64_t* hkeys;      // cell table
+    const int32_t* hval;
+    const int32_t* box;         // cell bounding box (6)
+    const int32_t* ncells;      // occupied cells (device scalar)
+    uint32_t lg;
+    double h;
+};
+
+struct KnnGrids {
+    KnnGrid g[kGrids];
+};
+
+// Exact k-NN, one thread per query, queries taken in the finest grid's cell order.
+//
+// A pass over grid g lists the k best pairs among the points of the cells it
+// visits.  If it cannot prove them final, its k-th pair P is still an upper
+// bound of the true k-th pair (its points are a subset of the cloud), so the
+// next pass (a) starts on the first coarser grid whose cells are at least
+// sqrt(d(P)) wide, (b) skips cells whose box lies farther than sqrt(d(P)), and
+// (c) keeps only candidates that do not exceed P.  Every point of the true
+// k best lies within sqrt(d(P)), so that pass still finds all of them.
+template <int KMAX>
+__global__ void __launch_bounds__(128) k_knn(const KnnGrid* __restrict__ grids, int64_t m, int k,
+                                             int32_t* __restrict__ nbr, double* __restrict__ nd2,
+                                             int32_t* __restrict__ hard, int32_t* __restrict__ n_hard) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m) return;
-    const double qx = sx[t], qy = sy[t], qz = sz[t];
-    int64_t cx, cy, cz;
-    unpack21(skeys[t], &cx, &cy, &cz);
-    const int32_t bx0 = box[0], by0 = box[1], bz0 = box[2], bx1 = box[3], by1 = box[4], bz1 = box[5];
-    const int64_t rmax = max(max(max(cx - bx0, bx1 - cx), max(cy - by0, by1 - cy)), max(cz - bz0, bz1 - cz));
+    const double qx = grids[0].sx[t], qy = grids[0].sy[t], qz = grids[0].sz[t];
     const int kk = (int)min((int64_t)k, m);
     double D[KMAX];
     int32_t I[KMAX];
-#pragma unroll
-    for (int s = 0; s < KMAX; ++s) {
-        D[s] = INFINITY;
-        I[s] = INT_MAX;
-    }
-    int64_t seen = 0;
-    bool brute = false;
-    for (int64_t r = 0;; ++r) {
-        if (r > 0 && (2 * r + 1) * (2 * r + 1) * (2 * r + 1) > 4 * nc + 64) {
-            brute = true;
-            break;
-        }
-        for (int64_t dx = -r; dx <= r; ++dx) {
-            const int64_t x = cx + dx;
-            if (x < bx0 || x > bx1) continue;
-            for (int64_t dy = -r; dy <= r; ++dy) {
-                const int64_t y = cy + dy;
-                if (y < by0 || y > by1) continue;
-                const bool edge = (dx == -r || dx == r || dy == -r || dy == r);
-                const int64_t step = (edge || r == 0) ? 1 : 2 * r;
-                for (int64_t dz = -r; dz <= r; dz += step) {
-                    const int64_t z = cz + dz;
-                    if (z < bz0 || z > bz1) continue;
-                    const int32_t c = cell_find(hkeys, hval, lg, pack21(x, y, z));
-                    if (c < 0) continue;
-                    const int32_t p0 = cstart[c], p1 = p0 + ccount[c];
-                    for (int32_t p = p0; p < p1; ++p) {
-                        knn_insert<KMAX>(D, I, kk, sqdist_rn(qx, qy, qz, sx[p], sy[p], sz[p]), cidx[p]);
-                        ++seen;
-                    }
-                }
-            }
-        }
-        if (r >= rmax) break;
-        if (seen >= kk) {
-            double kth = D[0];
-#pragma unroll
-            for (int s = 1; s < KMAX; ++s)
-                if (s == kk - 1) kth = D[s];
-            const double bx = fmin(qx - (double)(cx - r) * h, (double)(cx + r + 1) * h - qx);
-            const double by = fmin(qy - (double)(cy - r) * h, (double)(cy + r + 1) * h - qy);
-            const double bz = fmin(qz - (double)(cz - r) * h, (double)(cz + r + 1) * h - qz);
-            const double b = fmin(bx, fmin(by, bz));
-            if (b > 0.0 && kth < b * b * (1.0 - 1e-9)) break;
-        }
-    }
-    if (brute) {
+    double bD = INFINITY;   // bound carried between passes: the previous pass's k-th pair
+    int32_t bI = INT_MAX;
+    bool done = false;
+    int64_t scanned = 0;    // candidates read; past kBudget the query goes to the wave-wide pass
+#pragma unroll 1
+    for (int gi = 0; gi < kGrids && !done; ++gi) {
+        const KnnGrid g = grids[gi];
+        const double h = g.h;
+        const bool last = (gi == kGrids - 1);
+        if (!last && bD < INFINITY && h * h <= bD) continue;   // cells too small for the bound
+        const int64_t cx = (int64_t)floor(qx / h), cy = (int64_t)floor(qy / h), cz = (int64_t)floor(qz / h);
+        const int32_t bx0 = g.box[0], by0 = g.box[1], bz0 = g.box[2], bx1 = g.box[3], by1 = g.box[4],
+                      bz1 = g.box[5];
+        const int64_t rmax = max(max(max(cx - bx0, bx1 - cx), max(cy - by0, by1 - cy)), max(cz - bz0, bz1 - cz));
+        const int64_t nc = *g.ncells;
 #pragma unroll
         for (int s = 0; s < KMAX; ++s) {
             D[s] = INFINITY;
             I[s] = INT_MAX;
         }
-        for (int64_t p = 0; p < m; ++p)
-            knn_insert<KMAX>(D, I, kk, sqdist_rn(qx, qy, qz, sx[p], sy[p], sz[p]), cidx[p]);
-    }
-    const int32_t i = cidx[t];
-#pragma unroll
-    for (int s = 0; s < KMAX; ++s) {
-        if (s < k) {
-            const bool ok = s < kk;
-            nbr[(int64_t)i * k + s] = ok ? I[s] : -1;
-            nd2[(int64_t)i * k + s] = ok ? D[s] : INFINITY;
+        // threshold: a candidate is kept iff it does not exceed (wD, wI); while the
+        // list is not full that is the carried bound, then the list's k-th pair
+        double wD = bD;
+        int32_t wI = bI;
+        int filled = 0;
+        for (int64_t r = 0;; ++r) {
+            if (!last && r > kShells) break;                       // not settled: next grid
+            if (last && r > 0 && (2 * r + 1) * (2 * r + 1) * (2 * r + 1) > 4 * nc + 64) goto handover;
+            for (int64_t dx = -r; dx <= r; ++dx) {
+                const int64_t x = cx + dx;
+                if (x < bx0 || x > bx1) continue;
+                const double ex = fmax(0.0, fmax((double)x * h - qx, qx - (double)(x + 1) * h));
+                for (int64_t dy = -r; dy <= r; ++dy) {
+                    const int64_t y = cy + dy;
+                    if (y < by0 || y > by1) continue;
+                    const double ey = fmax(0.0, fmax((double)y * h - qy, qy - (double)(y + 1) * h));
+                    const bool edge = (dx == -r || dx == r || dy == -r || dy == r);
+                    const int64_t step = (edge || r == 0) ? 1 : 2 * r;
+                    for (int64_t dz = -r; dz <= r; dz += step) {
+                        const int64_t z = cz + dz;
+                        if (z < bz0 || z > bz1) continue;
+                        const double ez = fmax(0.0, fmax((double)z * h - qz, qz - (double)(z + 1) * h));
+                        // the cell's box is farther than the threshold: nothing in it can be kept
+                        // (margin for the rounding of the box and of the distances)
+                        if ((ex * ex + ey * ey + ez * ez) * (1.0 - 1e-9) > wD) continue;
+                        const int32_t c = cell_find(g.hkeys, g.hval, g.lg, pack21(x, y, z));
+                        if (c < 0) continue;
+                        const int32_t p0 = g.cstart[c], p1 = p0 + g.ccount[c];
+                        scanned += p1 - p0;
+                        if (scanned > kBudget) goto handover;
+                        for (int32_t p = p0; p < p1; ++p) {
+                            const double d = sqdist_rn(qx, qy, qz, g.sx[p], g.sy[p], g.sz[p]);
+                            const int32_t j = g.cidx[p];
+                            if (!pair_less(wD, wI, d, j)) {   // (d, j) <= threshold
+                                knn_insert<KMAX>(D, I, kk, d, j);
+                                if (++filled >= kk) kth_pair<KMAX>(D, I, kk, wD, wI);
+                            }
+                        }
+                    }
+                }
+            }
+            if (r >= rmax) {   // every occupied cell of this grid visited
+                done = true;
+                break;
+            }
+            if (filled >= kk) {
+                const double bx = fmin(qx - (double)(cx - r) * h, (double)(cx + r + 1) * h - qx);
+                const double by = fmin(qy - (double)(cy - r) * h, (double)(cy + r + 1) * h - qy);
+                const double bz = fmin(qz - (double)(cz - r) * h, (double)(cz + r + 1) * h - qz);
+                const double b = fmin(bx, fmin(by, bz));
+                if (b > 0.0 && wD < b * b * (1.0 - 1e-9)) {
+                    done = true;
+                    break;
+                }
+            }
         }
+        if (!done && filled >= kk) {
+            bD = wD;
+            bI = wI;
+        }
+    }
+    {
+        const int32_t i = grids[0].cidx[t];
+#pragma unroll
+        for (int s = 0; s < KMAX; ++s) {
+            if (s < k) {
+                const bool ok = s < kk;
+                nbr[(int64_t)i * k + s] = ok ? I[s] : -1;
+                nd2[(int64_t)i * k + s] = ok ? D[s] : INFINITY;
+            }
+        }
+        return;
+    }
+handover:
+    hard[atomicAdd(n_hard, 1)] = (int32_t)t;
+}
+
+// The queries the grid walk handed over: one wave per query scans every point
+// (each lane a strided share, its own k best in registers), then the lanes'
+// lists are merged by k rounds of a wave-wide minimum over their heads.
+template <int KMAX>
+__global__ void __launch_bounds__(64) k_knn_wave(const KnnGrid* __restrict__ grids, int64_t m, int k,
+                                                 const int32_t* __restrict__ hard, const int32_t* __restrict__ n_hard,
+                                                 uint32_t* __restrict__ next, int32_t* __restrict__ nbr,
+                                                 double* __restrict__ nd2) {
+    const KnnGrid g = grids[0];
+    const int lane = threadIdx.x;
+    const int kk = (int)min((int64_t)k, m);
+    for (;;) {
+        int32_t q = 0;
+        if (lane == 0) q = (int32_t)atomicAdd(next, 1u);
+        q = __shfl(q, 0);
+        if (q >= *n_hard) break;
+        const int32_t t = hard[q];
+        const double qx = g.sx[t], qy = g.sy[t], qz = g.sz[t];
+        double D[KMAX];
+        int32_t I[KMAX];
+#pragma unroll
+        for (int s = 0; s < KMAX; ++s) {
+            D[s] = INFINITY;
+            I[s] = INT_MAX;
+        }
+        double wD = INFINITY;
+        int32_t wI = INT_MAX;
+        int filled = 0;
+        for (int64_t p = lane; p < m; p += 64) {
+            const double d = sqdist_rn(qx, qy, qz, g.sx[p], g.sy[p], g.sz[p]);
+            const int32_t j = g.cidx[p];
+            if (!pair_less(wD, wI, d, j)) {
+                knn_insert<KMAX>(D, I, kk, d, j);
+                if (++filled >= kk) kth_pair<KMAX>(D, I, kk, wD, wI);
+            }
+        }
+        const int32_t i = g.cidx[t];
+        for (int o = 0; o < kk; ++o) {
+            double bd = D[0];
+            int32_t bj = I[0];
+#pragma unroll
+            for (int w = 32; w >= 1; w >>= 1) {
+                const double od = __shfl_xor(bd, w);
+                const int32_t oj = __shfl_xor(bj, w);
+                if (pair_less(od, oj, bd, bj)) {
+                    bd = od;
+                    bj = oj;
+                }
+            }
+            if (D[0] == bd && I[0] == bj) {   // this lane's head won: drop it
+#pragma unroll
+                for (int s = 0; s + 1 < KMAX; ++s) {
+                    D[s] = D[s + 1];
+                    I[s] = I[s + 1];
+                }
+                D[KMAX - 1] = INFINITY;
+                I[KMAX - 1] = INT_MAX;
+            }
+            if (lane == 0) {
+                nbr[(int64_t)i * k + o] = bj;
+                nd2[(int64_t)i * k + o] = bd;
+            }
+        }
+        if (lane == 0)
+            for (int o = kk; o < k; ++o) {
+                nbr[(int64_t)i * k + o] = -1;
+                nd2[(int64_t)i * k + o] = INFINITY;
+            }
     }
 }
 
@@ -378,36 +551,65 @@ __global__ void k_cov_normals(const double* __restrict__ xyz, const int32_t* __r
 
 int grid_of(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
 
+// Temporaries of one preprocessing call, carved from the context's workspace;
+// what does not fit is allocated and freed, and the workspace grows to the
+// call's total afterwards, so frames of similar size allocate nothing.
 struct Scratch {
+    vg_context* ctx;
+    size_t off = 0, need = 0;
     std::vector<void*> ptrs;
+    explicit Scratch(vg_context* c) : ctx(c) {}
     ~Scratch() {
+        (void)hipStreamSynchronize(ctx->stream);   // also on early error returns
         for (void* p : ptrs) (void)hipFree(p);
+        if (need > ctx->ws_bytes) {
+            if (ctx->ws) (void)hipFree(ctx->ws);
+            ctx->ws = nullptr;
+            ctx->ws_bytes = 0;
+            if (hipMalloc(&ctx->ws, need) == hipSuccess) ctx->ws_bytes = need;
+        }
     }
     template <typename T>
     hipError_t get(T** p, size_t count) {
+        const size_t bytes = (sizeof(T) * (count ? count : 1) + 255) & ~(size_t)255;
+        need += bytes;
+        if (ctx->ws && off + bytes <= ctx->ws_bytes) {
+            *p = (T*)((char*)ctx->ws + off);
+            off += bytes;
+            return hipSuccess;
+        }
         void* q = nullptr;
-        hipError_t e = hipMalloc(&q, sizeof(T) * (count ? count : 1));
+        hipError_t e = hipMalloc(&q, bytes);
         if (e == hipSuccess) ptrs.push_back(q);
         *p = (T*)q;
         return e;
     }
 };
 
-template <typename T>
-hipError_t owned(T** p, size_t count) {
-    return hipMalloc((void**)p, sizeof(T) * (count ? count : 1));
+// every output array of a cloud in one allocation
+hipError_t alloc_cloud(vg_cloud* c, int64_t m, int k) {
+    const size_t nd = (size_t)m * (3 + 6 + 6 + 3 + k), ni = (size_t)m * (1 + k);
+    void* b = nullptr;
+    hipError_t e = hipMalloc(&b, sizeof(double) * (nd ? nd : 1) + sizeof(int32_t) * (ni ? ni : 1));
+    if (e != hipSuccess) return e;
+    c->block = b;
+    double* d = (double*)b;
+    c->xyz = d;
+    c->cov = d + 3 * m;
+    c->cov_raw = d + 9 * m;
+    c->nrm = d + 15 * m;
+    c->d2 = d + 18 * m;
+    int32_t* i = (int32_t*)(d + (nd ? nd : 1));
+    c->counts = i;
+    c->nbr = i + m;
+    return hipSuccess;
 }
 
 }  // namespace
 
 void free_cloud(vg_cloud* c) {
-    (void)hipFree(c->xyz);
-    (void)hipFree(c->cov);
-    (void)hipFree(c->cov_raw);
-    (void)hipFree(c->nrm);
-    (void)hipFree(c->counts);
-    (void)hipFree(c->nbr);
-    (void)hipFree(c->d2);
+    if (c->block) (void)hipFree(c->block);
+    c->block = nullptr;
     c->xyz = c->cov = c->cov_raw = c->nrm = c->d2 = nullptr;
     c->counts = c->nbr = nullptr;
 }
@@ -417,19 +619,13 @@ vg_status preprocess_frame(vg_context* ctx, const double* d_xyz, int64_t n, doub
     hipStream_t st = ctx->stream;
     out->k = k;
     out->m = 0;
-    Scratch sc;
-    int32_t* d_small = nullptr;   // flag, voxel count, cell count, cell box
-    VG_HIP(sc.get(&d_small, 16));
     if (n == 0) {
-        VG_HIP(owned(&out->xyz, 0));
-        VG_HIP(owned(&out->cov, 0));
-        VG_HIP(owned(&out->cov_raw, 0));
-        VG_HIP(owned(&out->nrm, 0));
-        VG_HIP(owned(&out->counts, 0));
-        VG_HIP(owned(&out->nbr, 0));
-        VG_HIP(owned(&out->d2, 0));
+        VG_HIP(alloc_cloud(out, 0, k));
         return VG_OK;
     }
+    Scratch sc(ctx);
+    int32_t* d_small = nullptr;   // flag, voxel count, hand-over count and cursor
+    VG_HIP(sc.get(&d_small, 16));
     // 1. downsampling
     uint64_t *keys, *keys_s, *ukeys;
     int32_t *idx, *idx_s, *counts, *offsets;
@@ -465,64 +661,87 @@ vg_status preprocess_frame(vg_context* ctx, const double* d_xyz, int64_t n, doub
     const int64_t m = h_small[1];
     tb = tmp_bytes;
     VG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, counts, offsets, (int)m, st));
-    VG_HIP(owned(&out->xyz, 3 * m));
-    VG_HIP(owned(&out->cov, 6 * m));
-    VG_HIP(owned(&out->cov_raw, 6 * m));
-    VG_HIP(owned(&out->nrm, 3 * m));
-    VG_HIP(owned(&out->counts, m));
-    VG_HIP(owned(&out->nbr, (size_t)m * k));
-    VG_HIP(owned(&out->d2, (size_t)m * k));
+    VG_HIP(alloc_cloud(out, m, k));
     out->m = m;
-    const double h = 2.0 * r;
-    uint64_t *ckeys, *ckeys_s, *ucells;
-    int32_t *cidx, *cidx_s, *ccount, *cstart;
+    k_ds_centroids<<<grid_of(m), 256, 0, st>>>(d_xyz, idx_s, offsets, counts, m, out->xyz, out->counts);
+    VG_HIP(hipGetLastError());
+    // 2. grids of cells and the neighbour search (no host round trip: the cell
+    // counts stay on the device, tables are sized for m cells)
+    uint32_t lg = 6;
+    while ((1ull << lg) < 2ull * (uint64_t)m) ++lg;
+    KnnGrids G{};
+    int32_t* d_grid_small = nullptr;   // per grid: box (6), cell count, pad
+    VG_HIP(sc.get(&d_grid_small, 8 * kGrids));
+    {
+        std::vector<int32_t> init(8 * kGrids);
+        for (int gi = 0; gi < kGrids; ++gi) {
+            int32_t* b = init.data() + 8 * gi;
+            b[0] = b[1] = b[2] = INT32_MAX;
+            b[3] = b[4] = b[5] = INT32_MIN;
+            b[6] = b[7] = 0;
+        }
+        VG_HIP(hipMemcpyAsync(d_grid_small, init.data(), sizeof(int32_t) * init.size(), hipMemcpyHostToDevice, st));
+        VG_HIP(hipStreamSynchronize(st));   // init lives on the host stack
+    }
+    uint64_t *ckeys, *ucells;
+    int32_t* cidx;
     VG_HIP(sc.get(&ckeys, m));
-    VG_HIP(sc.get(&ckeys_s, m));
     VG_HIP(sc.get(&ucells, m));
     VG_HIP(sc.get(&cidx, m));
-    VG_HIP(sc.get(&cidx_s, m));
-    VG_HIP(sc.get(&ccount, m));
-    VG_HIP(sc.get(&cstart, m));
-    k_ds_centroids<<<grid_of(m), 256, 0, st>>>(d_xyz, idx_s, offsets, counts, m, h, out->xyz, out->counts, ckeys,
-                                                cidx, d_small + 8);
-    VG_HIP(hipGetLastError());
-    // 2. grid of cells and the neighbour search
-    tb = tmp_bytes;
-    VG_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, ckeys, ckeys_s, cidx, cidx_s, (int)m, 0, 3 * kPBits, st));
-    tb = tmp_bytes;
-    VG_HIP(hipcub::DeviceRunLengthEncode::Encode(tmp, tb, ckeys_s, ucells, ccount, d_small + 2, (int)m, st));
-    int32_t h_nc = 0;
-    VG_HIP(hipMemcpyAsync(&h_nc, d_small + 2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    VG_HIP(hipStreamSynchronize(st));
-    const int64_t nc = h_nc;
-    tb = tmp_bytes;
-    VG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, ccount, cstart, (int)nc, st));
-    uint32_t lg = 6;
-    while ((1ull << lg) < 2ull * (uint64_t)nc) ++lg;
-    uint64_t* hkeys;
-    int32_t* hval;
-    VG_HIP(sc.get(&hkeys, (size_t)1 << lg));
-    VG_HIP(sc.get(&hval, (size_t)1 << lg));
-    k_fill_u64p<<<grid_of((int64_t)1 << lg), 256, 0, st>>>(hkeys, (int64_t)1 << lg, kPEmpty);
-    VG_HIP(hipGetLastError());
-    k_cells_insert<<<grid_of(nc), 256, 0, st>>>(ucells, nc, hkeys, hval, lg);
-    VG_HIP(hipGetLastError());
-    double *sx, *sy, *sz;
-    VG_HIP(sc.get(&sx, m));
-    VG_HIP(sc.get(&sy, m));
-    VG_HIP(sc.get(&sz, m));
-    k_cells_gather<<<grid_of(m), 256, 0, st>>>(out->xyz, cidx_s, m, sx, sy, sz);
-    VG_HIP(hipGetLastError());
+    double h = 2.0 * r;
+    for (int gi = 0; gi < kGrids; ++gi, h *= 2.0) {
+        KnnGrid& g = G.g[gi];
+        uint64_t* ckeys_s;
+        int32_t *cidx_s, *ccount, *cstart, *hval;
+        uint64_t* hkeys;
+        double *sx, *sy, *sz;
+        VG_HIP(sc.get(&ckeys_s, m));
+        VG_HIP(sc.get(&cidx_s, m));
+        VG_HIP(sc.get(&ccount, m));
+        VG_HIP(sc.get(&cstart, m));
+        VG_HIP(sc.get(&hkeys, (size_t)1 << lg));
+        VG_HIP(sc.get(&hval, (size_t)1 << lg));
+        VG_HIP(sc.get(&sx, m));
+        VG_HIP(sc.get(&sy, m));
+        VG_HIP(sc.get(&sz, m));
+        int32_t* box = d_grid_small + 8 * gi;
+        k_grid_keys<<<grid_of(m), 256, 0, st>>>(out->xyz, m, h, ckeys, cidx, box);
+        VG_HIP(hipGetLastError());
+        tb = tmp_bytes;
+        VG_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, ckeys, ckeys_s, cidx, cidx_s, (int)m, 0, 3 * kPBits, st));
+        k_fill_i32<<<grid_of(m), 256, 0, st>>>(ccount, m, 0);
+        VG_HIP(hipGetLastError());
+        tb = tmp_bytes;
+        VG_HIP(hipcub::DeviceRunLengthEncode::Encode(tmp, tb, ckeys_s, ucells, ccount, box + 6, (int)m, st));
+        tb = tmp_bytes;
+        VG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, ccount, cstart, (int)m, st));
+        k_fill_u64p<<<grid_of((int64_t)1 << lg), 256, 0, st>>>(hkeys, (int64_t)1 << lg, kPEmpty);
+        VG_HIP(hipGetLastError());
+        k_cells_insert<<<grid_of(m), 256, 0, st>>>(ucells, box + 6, hkeys, hval, lg);
+        VG_HIP(hipGetLastError());
+        k_cells_gather<<<grid_of(m), 256, 0, st>>>(out->xyz, cidx_s, m, sx, sy, sz);
+        VG_HIP(hipGetLastError());
+        g = KnnGrid{sx, sy, sz, cidx_s, cstart, ccount, hkeys, hval, box, box + 6, lg, h};
+    }
+    KnnGrid* d_grids = nullptr;
+    VG_HIP(sc.get(&d_grids, kGrids));
+    VG_HIP(hipMemcpyAsync(d_grids, G.g, sizeof(G.g), hipMemcpyHostToDevice, st));
+    int32_t* d_hard = nullptr;
+    VG_HIP(sc.get(&d_hard, m));
+    int32_t* d_nhard = d_small + 4;                      // zeroed with d_small
+    uint32_t* d_next = (uint32_t*)(d_small + 5);
     const int kb = 128;
-    if (k <= 8)
-        k_knn<8><<<grid_of(m, kb), kb, 0, st>>>(sx, sy, sz, cidx_s, ckeys_s, cstart, ccount, hkeys, hval, lg,
-                                                d_small + 8, m, nc, k, h, out->nbr, out->d2);
-    else if (k <= 16)
-        k_knn<16><<<grid_of(m, kb), kb, 0, st>>>(sx, sy, sz, cidx_s, ckeys_s, cstart, ccount, hkeys, hval, lg,
-                                                 d_small + 8, m, nc, k, h, out->nbr, out->d2);
-    else
-        k_knn<32><<<grid_of(m, kb), kb, 0, st>>>(sx, sy, sz, cidx_s, ckeys_s, cstart, ccount, hkeys, hval, lg,
-                                                 d_small + 8, m, nc, k, h, out->nbr, out->d2);
+    const int waves = 2048;
+    if (k <= 8) {
+        k_knn<8><<<grid_of(m, kb), kb, 0, st>>>(d_grids, m, k, out->nbr, out->d2, d_hard, d_nhard);
+        k_knn_wave<8><<<waves, 64, 0, st>>>(d_grids, m, k, d_hard, d_nhard, d_next, out->nbr, out->d2);
+    } else if (k <= 16) {
+        k_knn<16><<<grid_of(m, kb), kb, 0, st>>>(d_grids, m, k, out->nbr, out->d2, d_hard, d_nhard);
+        k_knn_wave<16><<<waves, 64, 0, st>>>(d_grids, m, k, d_hard, d_nhard, d_next, out->nbr, out->d2);
+    } else {
+        k_knn<32><<<grid_of(m, kb), kb, 0, st>>>(d_grids, m, k, out->nbr, out->d2, d_hard, d_nhard);
+        k_knn_wave<32><<<waves, 64, 0, st>>>(d_grids, m, k, d_hard, d_nhard, d_next, out->nbr, out->d2);
+    }
     VG_HIP(hipGetLastError());
     // 3. covariances and normals
     k_cov_normals<<<grid_of(m), 256, 0, st>>>(out->xyz, out->nbr, m, k, sensor[0], sensor[1], sensor[2], out->cov,

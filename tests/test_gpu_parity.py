@@ -122,6 +122,15 @@ def test_config2_batch(vg, c2):
     for _ in range(3):
         e3, H3, b3, _ = batch.linearize(poses)
         assert np.array_equal(e, e3) and np.array_equal(H, H3) and np.array_equal(b, b3)
+    # both tile orders and other grid sizes (same block and tile: the same tiles
+    # reduce to the same rows in the same order): bitwise identical
+    info = batch.info()
+    for order, bpc in ((1, 1), (2, 8), (2, 2)):
+        _, _, other = vgicp.build_workload(ctx, c2, tile_order=order, block=info["block_threads"],
+                                           tile=info["tile_points"], blocks_per_cu=bpc)
+        e4, H4, b4, _ = other.linearize(poses)
+        assert np.array_equal(e, e4) and np.array_equal(H, H4) and np.array_equal(b, b4)
+        other.close()
     plain.close()
     batch.close()
 

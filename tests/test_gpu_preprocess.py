@@ -180,6 +180,29 @@ def test_edge_cases(vg):
     compare_full(device(vgicp, ctx, far, 0.05, 10, s), far, 0.05, 10, s)
 
 
+def test_isolated_cluster_near_dense_surfaces(vg):
+    """A 5-point cluster 10 m from dense walls: its 10 nearest neighbours need a
+    search radius of ~10 m through thousands of wall points, which the grid walk
+    hands over to the wave-wide pass."""
+    vgicp, ctx = vg
+    rng = np.random.default_rng(3)
+    u = rng.uniform(-15, 15, size=(40000, 2))
+    walls = np.concatenate([np.stack([u[:20000, 0], np.full(20000, 10.0), rng.uniform(0, 3, 20000)], 1),
+                            np.stack([np.full(20000, -10.0), u[20000:, 1], rng.uniform(0, 3, 20000)], 1)])
+    cluster = np.array([0.0, 0.0, 1.5]) + rng.uniform(-0.3, 0.3, size=(5, 3))
+    xyz = np.concatenate([walls, cluster])
+    sensor = np.array([0.0, 0.0, 1.0])
+    dev = device(vgicp, ctx, xyz, 0.1, 10, sensor)
+    c, _, _ = pp.downsample(xyz, 0.1)
+    assert np.array_equal(dev["xyz"], c)
+    far = np.nonzero(np.linalg.norm(c - [0.0, 0.0, 1.5], axis=1) < 1.0)[0]
+    q = np.concatenate([far, np.random.default_rng(0).choice(len(c), 200, replace=False)])
+    idx, d2 = pp.knn(c, 10, queries=q)
+    assert np.array_equal(dev["nbr"][q], idx.astype(np.int32))
+    assert np.array_equal(dev["d2"][q], d2)
+    check_rows({key: dev[key][q] for key in ("cov", "cov_raw", "normals")}, c, q, idx, sensor)
+
+
 def test_invalid_arguments(vg):
     vgicp, ctx = vg
     from paper_2407_10344_amd._lib import VGError

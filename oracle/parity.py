@@ -91,3 +91,40 @@ def check_factor(batch, f, pose, ofac, e_dev, H_dev, b_dev, rel=REL):
     errs = {"e": rel_err(e_dev, e), "H": rel_err(H_dev, H), "b": rel_err(b_dev, b)}
     assert errs["e"] <= rel and errs["H"] <= rel and errs["b"] <= rel, (errs, stats)
     return errs, stats
+
+
+def _packed(vmap, level):
+    """Voxel keys of an oracle level packed into one int64 each, in the same (lexicographic) order."""
+    cache = vmap.__dict__.setdefault("_packed_keys", {})
+    if level not in cache:
+        k = vmap.levels[level][0]
+        cache[level] = ((k[:, 0] + (1 << 20)) << 42) | ((k[:, 1] + (1 << 20)) << 21) | (k[:, 2] + (1 << 20))
+    return cache[level]
+
+
+def oracle_voxel_index(vmap, level, key):
+    """Index of voxel `key` in the oracle's level (lexicographic order), -1 if absent."""
+    pk = _packed(vmap, level)
+    q = ((int(key[0]) + (1 << 20)) << 42) | ((int(key[1]) + (1 << 20)) << 21) | (int(key[2]) + (1 << 20))
+    i = int(np.searchsorted(pk, q))
+    return i if i < len(pk) and pk[i] == q else -1
+
+
+def frozen_from_device_keys(ofac, pose, keys_dev, found_dev, band=BAND):
+    """Per point and level, the oracle voxel index of the device's correspondence
+    (-1 where the device found none or discarded the point), for the oracle's
+    frozen-correspondence evaluate / gradient.  Asserts that keys agree away
+    from the face band."""
+    tr = ofac.linearize(pose, trace=True)
+    keys_o, vidx_o, face = tr["keys"], tr["vidx"], tr["face"]
+    mism = np.any(keys_dev != keys_o, axis=2)
+    assert not (mism & ~(face < band)).any(), "device keys differ from the oracle away from voxel faces"
+    fz = vidx_o.copy()
+    fz[found_dev != 1] = -1
+    for k, l in zip(*np.nonzero(mism & (found_dev == 1))):
+        fz[k, l] = oracle_voxel_index(ofac.vmap, l, keys_dev[k, l])
+        assert fz[k, l] >= 0
+    same = ~mism & (found_dev == 1)
+    assert np.all(vidx_o[same] >= 0), "device found a voxel the oracle does not have"
+    return fz, int(mism.sum())
+

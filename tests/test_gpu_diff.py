@@ -16,6 +16,7 @@ import torch
 from scipy.linalg import expm, logm
 
 import oracle
+from oracle.parity import frozen_from_device_keys
 import synth
 from oracle.parity import rel_err
 
@@ -190,11 +191,13 @@ def test_differentiation_batch_full_size(vg):
     for f in (0, 31, 63):
         s, t = cfg["factors"][f]
         of = oracle.factor_from_clouds(cfg["sources"][s], cfg["targets"][t], cfg["resolutions"])
-        tr = of.linearize(poses[f], trace=True)
-        if np.any(tr["face"] < 1e-5):
-            continue     # ambiguous correspondences: covered by the tests above
-        g_o, gm_o = of.gradient(poses[f])
+        # points within 1e-5 m of a voxel face may take either voxel: the oracle
+        # gradient is taken on the device's correspondences (frozen), W recomputed
+        keys_d, found_d = batch.correspondences(poses[f], f)
+        fz, n_face = frozen_from_device_keys(of, poses[f], keys_d, found_d)
+        g_o, gm_o = of.gradient(poses[f], frozen=fz)
         row0, n = batch.source_rows[id(srcs[s])]
-        assert rel_err(gxi[f], g_o) <= 1e-5
-        assert rel_err(gp[row0:row0 + n].astype(np.float64), gm_o) <= 1e-5
+        ex, ep = rel_err(gxi[f], g_o), rel_err(gp[row0:row0 + n].astype(np.float64), gm_o)
+        print("factor", f, "near-face choices", n_face, "rel err xi %.3g points %.3g" % (ex, ep), flush=True)
+        assert ex <= 1e-5 and ep <= 1e-5
     batch.close()

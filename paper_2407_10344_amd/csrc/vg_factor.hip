@@ -142,12 +142,10 @@ struct TileShared {
 template <int PREC>
 struct RawPoint {
     float x[3];   // kC32: offset from the chunk anchor; kN32: absolute position
-    float cv[6];
 };
 template <>
 struct RawPoint<kF64> {
     double x[3];
-    double cv[6];
 };
 
 template <int PREC>
@@ -155,25 +153,44 @@ __device__ __forceinline__ void load_point(const FactorDesc* __restrict__ Fp, in
                                            RawPoint<PREC>& p) {
     if constexpr (PREC == kC32) {
         const auto X = gbl(Fp->dxyz);
-        const auto Cv = gbl(Fp->cov);
 #pragma unroll
         for (int a = 0; a < 3; ++a) p.x[a] = X[a * n_pad + i];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) p.cv[k] = Cv[k * n_pad + i];
     } else if constexpr (PREC == kN32) {
         const auto X = gbl(Fp->axyz);
-        const auto Cv = gbl(Fp->cov);
 #pragma unroll
         for (int a = 0; a < 3; ++a) p.x[a] = X[a * n_pad + i];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) p.cv[k] = Cv[k * n_pad + i];
     } else {
         const auto X = gbl(Fp->xyz64);
-        const auto Cv = gbl(Fp->cov64);
 #pragma unroll
         for (int a = 0; a < 3; ++a) p.x[a] = X[a * n_pad + i];
+    }
+}
+
+// S = R C R^T of point i.  The covariance is read only here, at the point's first
+// hit: most points find no voxel, and their covariances are never loaded.
+template <int PREC, typename TS, typename T>
+__device__ __forceinline__ void point_S(const FactorDesc* __restrict__ Fp, int64_t i, int64_t n_pad,
+                                        const double* P, const T* R, TS* S) {
+    if constexpr (PREC == kC32) {
+        const auto Cv = gbl(Fp->cov);
+        double R64[9], C64[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) p.cv[k] = Cv[k * n_pad + i];
+        for (int k = 0; k < 6; ++k) C64[k] = (double)Cv[k * n_pad + i];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) R64[k] = P[k];
+        rotate_cov(R64, C64, S);
+    } else if constexpr (PREC == kN32) {
+        const auto Cv = gbl(Fp->cov);
+        float C[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) C[k] = Cv[k * n_pad + i];
+        rotate_cov(R, C, S);
+    } else {
+        const auto Cv = gbl(Fp->cov64);
+        double C[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) C[k] = Cv[k * n_pad + i];
+        rotate_cov(R, C, S);
     }
 }
 
@@ -327,7 +344,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
             if (i >= n) continue;
             // ---- load the point, transform it
             // yl: transformed position (kC32: relative to the anchor's coarse voxel corner)
-            T x[3], cv[6], z[3];
+            T x[3], z[3];
             T yl[3];          // transformed position (kC32: FP32, relative to the anchor's coarse voxel)
             bool vis = true;
             if constexpr (PREC == kC32) {
@@ -337,8 +354,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 // positions down to centimetres, so for hits the offset from the
                 // anchor is rotated and placed relative to the voxel centre in FP64.
                 const float dx = cur.x[0], dy = cur.x[1], dz = cur.x[2];
-#pragma unroll
-                for (int k = 0; k < 6; ++k) cv[k] = cur.cv[k];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     yl[a] = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
@@ -356,8 +371,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
 #pragma unroll
                 for (int a = 0; a < 3; ++a) x[a] = cur.x[a];
 #pragma unroll
-                for (int k = 0; k < 6; ++k) cv[k] = cur.cv[k];
-#pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     z[a] = R[3 * a] * x[0] + R[3 * a + 1] * x[1] + R[3 * a + 2] * x[2];
                     yl[a] = z[a] + tt[a];
@@ -370,8 +383,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
             } else {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) x[a] = cur.x[a];
-#pragma unroll
-                for (int k = 0; k < 6; ++k) cv[k] = cur.cv[k];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     z[a] = R[3 * a] * x[0] + R[3 * a + 1] * x[1] + R[3 * a + 2] * x[2];
@@ -444,24 +455,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 if (v < 0) continue;
                 inl[l] += 1;
                 if constexpr (MODE == kCount) continue;
-                if (!haveS) {
-                    if constexpr (PREC == kC32) {
-                        double R64[9], C64[6];
-#pragma unroll
-                        for (int k = 0; k < 9; ++k) R64[k] = P[k];
-#pragma unroll
-                        for (int k = 0; k < 6; ++k) C64[k] = (double)cv[k];
-                        rotate_cov(R64, C64, S);
-                    } else {
-                        rotate_cov(R, cv, S);
-                    }
-                    haveS = true;
-                }
                 T mv[3];
                 T W[6];
                 if constexpr (PREC == kC32) {
+                    // the voxel record's loads are issued before the covariance's (first
+                    // hit only), so the two round trips overlap
                     const auto r4 = gbl(reinterpret_cast<const f32x4*>(lv.rec32 + (int64_t)v * kRec32));
                     const f32x4 q0 = r4[0], q1 = r4[1], q2 = r4[2], q3 = r4[3];
+                    if (!haveS) {
+                        point_S<PREC>(Fp, i, n_pad, P, R, S);
+                        haveS = true;
+                    }
                     mv[0] = q0.x; mv[1] = q0.y; mv[2] = q0.z;
                     double M[6], W64[6];
                     M[0] = ((double)q0.w + (double)q2.y) + S[0];
@@ -485,6 +489,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         const f64x2 q0 = r2[0], q1 = r2[1], q2 = r2[2], q3 = r2[3], q4 = r2[4];
                         mv[0] = q0.x; mv[1] = q0.y; mv[2] = q1.x;
                         cvv[0] = q1.y; cvv[1] = q2.x; cvv[2] = q2.y; cvv[3] = q3.x; cvv[4] = q3.y; cvv[5] = q4.x;
+                    }
+                    if (!haveS) {
+                        point_S<PREC>(Fp, i, n_pad, P, R, S);
+                        haveS = true;
                     }
                     T M[6];
 #pragma unroll

@@ -138,6 +138,20 @@ struct TileShared {
     float vc[kMaxTileChunks * 3];      // anchor - T^-1 c (surface validation)
 };
 
+// Per-wave queue of (point, level) hits of the compacted linearization: the
+// probe (keys, bounding box, block-table lookup) runs on every point, the
+// expensive part (record gather, fused covariance and its inverse, residual,
+// 28 terms) only on full waves of hits.  Ring of 128 entries: a push adds at
+// most 64 (one level of one chunk) and a full wave of 64 is drained as soon as
+// 64 are queued, so at most 127 are ever held.
+constexpr int kQueue = 128;
+struct HitQueue {
+    float x[kQueue], y[kQueue], z[kQueue];   // point offset from its chunk anchor
+    int32_t pt[kQueue];                      // point index in the source (internal order)
+    int32_t rec[kQueue];                     // voxel record index
+    int32_t cl[kQueue];                      // chunk in tile (bits 2..) and level (bits 0..1)
+};
+
 // Raw per-point inputs of one precision mode, loaded one chunk ahead.
 template <int PREC>
 struct RawPoint {
@@ -194,6 +208,46 @@ __device__ __forceinline__ void point_S(const FactorDesc* __restrict__ Fp, int64
     }
 }
 
+// Terms of one queued hit (compensated mode): the same arithmetic as the
+// uncompacted path, with the point's chunk and level taken from the entry.
+template <typename A>
+__device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restrict__ Fp, const TileShared& sh,
+                                              const double* P, const float* R, int64_t n_pad, float dx, float dy,
+                                              float dz, int32_t i, int32_t v, int32_t cl) {
+    const int c = cl >> 2, l = cl & 3;
+    const LevelDesc& lv = Fp->lv[l];
+    const auto r4 = gbl(reinterpret_cast<const f32x4*>(lv.rec32 + (int64_t)v * kRec32));
+    const f32x4 q0 = r4[0], q1 = r4[1], q2 = r4[2], q3 = r4[3];
+    double S[6];
+    point_S<kC32>(Fp, (int64_t)i, n_pad, P, R, S);
+    float jf[3], z[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float yl = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
+        jf[a] = floorf(yl * lv.inv_r);
+        z[a] = sh.za[3 * c + a] + fmaf(R[3 * a + 2], dz, fmaf(R[3 * a + 1], dy, R[3 * a] * dx));
+    }
+    double M[6], W64[6];
+    M[0] = ((double)q0.w + (double)q2.y) + S[0];
+    M[1] = ((double)q1.x + (double)q2.z) + S[1];
+    M[2] = ((double)q1.y + (double)q2.w) + S[2];
+    M[3] = ((double)q1.z + (double)q3.x) + S[3];
+    M[4] = ((double)q1.w + (double)q3.y) + S[4];
+    M[5] = ((double)q2.x + (double)q3.z) + S[5];
+    sym3_inverse(M, W64);
+    float W[6], d[3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) W[k] = (float)W64[k];
+    const float mv[3] = {q0.x, q0.y, q0.z};
+    const double ddx = dx, ddy = dy, ddz = dz;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double y64 = sh.frac[3 * c + a] + (P[3 * a] * ddx + P[3 * a + 1] * ddy + P[3 * a + 2] * ddz);
+        d[a] = (float)((double)mv[a] - (y64 - ((double)jf[a] + 0.5) * lv.r64));
+    }
+    add_lin_terms(acc, d, W, z);
+}
+
 // Register budget: 4 waves per SIMD (<= 128 VGPRs) for the FP32 modes; the
 // FP64 mode needs more and runs at what its register count allows.
 template <int PREC, bool KH>
@@ -218,7 +272,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
     constexpr int NW = BLOCK / 64;
     constexpr bool KAHAN = KH && (PREC == kC32);
     constexpr int NT = (MODE == kLin) ? kTerms : (MODE == kBwd ? 6 : 1);
+    constexpr bool CMP = (MODE == kLin && PREC == kC32);   // compacted hits
     __shared__ TileShared sh;
+    using QueueT = typename std::conditional<CMP, HitQueue, int32_t>::type;
+    __shared__ QueueT s_q[CMP ? NW : 1];
     __shared__ double s_red[NW][kRow];
     __shared__ int32_t s_tile;
     const int lane = threadIdx.x & 63;
@@ -327,6 +384,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
         double ge = 0.0;
         if constexpr (MODE == kBwd) ge = grad_e[tile.factor];
 
+        int q_head = 0, q_count = 0;   // this wave's hit queue (wave-uniform)
+
         // each wave walks chunks wave, wave + NW, ...; the next chunk's point is
         // loaded before the current one is processed, so its latency overlaps
         RawPoint<PREC> nxt;
@@ -340,6 +399,61 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
             if (c + NW < tile.nchunks) {
                 const int64_t in = i + (int64_t)NW * kChunk;
                 if (in < n) load_point<PREC>(Fp, in, n_pad, nxt);
+            }
+            if constexpr (CMP) {
+                // ---- probe every point, queue its hits, drain full waves of hits
+                HitQueue& Q = s_q[wave];
+                const bool live = i < n;
+                const float dx = cur.x[0], dy = cur.x[1], dz = cur.x[2];
+                float yl[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    yl[a] = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
+                bool vis = live;
+                if (live && validate) {
+                    const float sv = (sh.vc[3 * c + 0] + dx) * Fp->nrm[i] + (sh.vc[3 * c + 1] + dy) * Fp->nrm[n_pad + i] +
+                                     (sh.vc[3 * c + 2] + dz) * Fp->nrm[2 * n_pad + i];
+                    vis = !(sv > 0.0f);
+                }
+#pragma unroll
+                for (int l = 0; l < kMaxLevels; ++l) {
+                    if (l >= L) break;
+                    const LevelDesc& lv = Fp->lv[l];
+                    int32_t v = -1;
+                    if (vis) {
+                        int64_t kq[3];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            kq[a] = (int64_t)sh.kb[3 * c + a] * lv.scale + (int64_t)floorf(yl[a] * lv.inv_r);
+                        if (kq[0] >= lv.kmin[0] && kq[0] <= lv.kmax[0] && kq[1] >= lv.kmin[1] && kq[1] <= lv.kmax[1] &&
+                            kq[2] >= lv.kmin[2] && kq[2] <= lv.kmax[2])
+                            v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
+                    }
+                    const bool hit = v >= 0;
+                    inl[l] += hit ? 1 : 0;
+                    const uint64_t mask = __ballot(hit);
+                    const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                    if (hit) {
+                        const int e = (q_head + q_count + below) & (kQueue - 1);
+                        Q.x[e] = dx;
+                        Q.y[e] = dy;
+                        Q.z[e] = dz;
+                        Q.pt[e] = (int32_t)i;
+                        Q.rec[e] = v;
+                        Q.cl[e] = (c << 2) | l;
+                    }
+                    q_count += __popcll(mask);
+                    if (q_count >= kChunk) {
+                        __builtin_amdgcn_wave_barrier();
+                        const int e = (q_head + lane) & (kQueue - 1);
+                        cmp_hit_terms(acc, Fp, sh, P, R, n_pad, Q.x[e], Q.y[e], Q.z[e], Q.pt[e], Q.rec[e], Q.cl[e]);
+                        q_head = (q_head + kChunk) & (kQueue - 1);
+                        q_count -= kChunk;
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+                continue;
             }
             if (i >= n) continue;
             // ---- load the point, transform it
@@ -563,6 +677,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         }
                     }
                 }
+            }
+        }
+        if constexpr (CMP) {
+            // the last, partial wave of queued hits
+            if (q_count > 0) {
+                __builtin_amdgcn_wave_barrier();
+                if (lane < q_count) {
+                    HitQueue& Q = s_q[wave];
+                    const int e = (q_head + lane) & (kQueue - 1);
+                    cmp_hit_terms(acc, Fp, sh, P, R, n_pad, Q.x[e], Q.y[e], Q.z[e], Q.pt[e], Q.rec[e], Q.cl[e]);
+                }
+                __builtin_amdgcn_wave_barrier();
             }
         }
         // ---------------------------------------------------------------- reduction of the tile

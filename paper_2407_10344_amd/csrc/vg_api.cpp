@@ -566,7 +566,6 @@ void fill_factor(vg_batch* b, int64_t f, const double* viewpoints) {
         q.recN = lv.recN;
         q.rec64 = lv.rec64;
         q.log2cap = lv.log2cap;
-        q.bmap = lv.bmap;
         q.scale = (int32_t)std::llround(rmax / lv.r);
         q.r = (float)lv.r;
         q.inv_r = (float)(1.0 / lv.r);
@@ -576,8 +575,6 @@ void fill_factor(vg_batch* b, int64_t f, const double* viewpoints) {
             q.K0[a] = lv.K0[a];
             q.kmin[a] = lv.kmin[a];
             q.kmax[a] = lv.kmax[a];
-            q.bmin[a] = lv.bmin[a];
-            q.bdim[a] = lv.bdim[a];
         }
     }
     b->h_fac[f] = d;

@@ -78,18 +78,6 @@ __device__ __forceinline__ int32_t lookup(const uint64_t* __restrict__ slots, ui
     return -1;
 }
 
-// Block occupancy test of relative key (kx, ky, kz), which must lie inside the
-// level's key box: false means no voxel of its 4x4x4 block exists, so the table
-// probe can be skipped.  Levels without a bitmap always pass.
-__device__ __forceinline__ bool block_occupied(const LevelDesc& lv, int64_t kx, int64_t ky, int64_t kz) {
-    if (lv.bmap == nullptr) return true;
-    const int32_t bx = (int32_t)((kx + kKeyBias) >> kBlockShift) - lv.bmin[0];
-    const int32_t by = (int32_t)((ky + kKeyBias) >> kBlockShift) - lv.bmin[1];
-    const int32_t bz = (int32_t)((kz + kKeyBias) >> kBlockShift) - lv.bmin[2];
-    const uint32_t bit = (uint32_t)((bx * lv.bdim[1] + by) * lv.bdim[2] + bz);
-    return (gbl(lv.bmap)[bit >> 5] >> (bit & 31)) & 1u;
-}
-
 // 1/x without the correctly rounded division sequence: hardware reciprocal
 // refined by Newton steps (two for FP64, each doubling the correct bits).
 __device__ __forceinline__ float recip(float x) {

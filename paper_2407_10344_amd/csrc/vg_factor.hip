@@ -426,7 +426,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         for (int a = 0; a < 3; ++a)
                             kq[a] = (int64_t)sh.kb[3 * c + a] * lv.scale + (int64_t)floorf(yl[a] * lv.inv_r);
                         if (kq[0] >= lv.kmin[0] && kq[0] <= lv.kmax[0] && kq[1] >= lv.kmin[1] && kq[1] <= lv.kmax[1] &&
-                            kq[2] >= lv.kmin[2] && kq[2] <= lv.kmax[2] && block_occupied(lv, kq[0], kq[1], kq[2]))
+                            kq[2] >= lv.kmin[2] && kq[2] <= lv.kmax[2])
                             v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
                     }
                     const bool hit = v >= 0;
@@ -565,7 +565,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 if (!(kq[0] >= lv.kmin[0] && kq[0] <= lv.kmax[0] && kq[1] >= lv.kmin[1] && kq[1] <= lv.kmax[1] &&
                       kq[2] >= lv.kmin[2] && kq[2] <= lv.kmax[2]))
                     continue;
-                if (!block_occupied(lv, kq[0], kq[1], kq[2])) continue;
                 const int32_t v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
                 if (v < 0) continue;
                 inl[l] += 1;

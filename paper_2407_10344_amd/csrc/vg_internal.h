@@ -50,9 +50,6 @@ struct LevelDesc {
     double r64, inv_r64;
     int64_t K0[3];           // absolute key of the map origin at this level
     int32_t kmin[3], kmax[3];// bounding box of the level's relative keys (empty: min > max)
-    const uint32_t* bmap;    // occupancy bit per 4x4x4 block inside the key box, or nullptr
-    int32_t bmin[3];         // block coordinate ((key + 8192) >> 2) of the bitmap origin
-    int32_t bdim[3];         // blocks per axis covered by the bitmap
 };
 
 // One factor: a source cloud (internal Morton order) matched into a target map.
@@ -98,8 +95,6 @@ struct Level {
     int32_t* counts = nullptr;  // V, canonical order
     int32_t* lex2rec = nullptr; // V: canonical index -> record index (records are block ordered)
     int32_t kmin[3] = {1, 1, 1}, kmax[3] = {0, 0, 0};   // relative key bounding box
-    uint32_t* bmap = nullptr;   // block occupancy bitmap over the key box (nullptr if too large)
-    int32_t bmin[3] = {0, 0, 0}, bdim[3] = {0, 0, 0};
 };
 
 }  // namespace vg

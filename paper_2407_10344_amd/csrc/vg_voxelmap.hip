@@ -145,27 +145,6 @@ __global__ void k_level_bbox(const uint64_t* __restrict__ ukeys, int64_t V, int3
     }
 }
 
-// One bit per occupied 4x4x4 block inside the level's key box: the tile kernel
-// tests it before hashing, so points in empty space skip the table probe.
-__global__ void k_block_bitmap(const uint64_t* __restrict__ ublocks, int64_t NB, int32_t b0, int32_t b1,
-                               int32_t b2, int32_t d0, int32_t d1, int32_t d2, uint32_t* __restrict__ bmap) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= NB) return;
-    const uint64_t bk = ublocks[i];
-    const uint64_t m = (1ull << kBlockBits) - 1;
-    const int32_t bx = (int32_t)((bk >> (2 * kBlockBits)) & m) - b0;
-    const int32_t by = (int32_t)((bk >> kBlockBits) & m) - b1;
-    const int32_t bz = (int32_t)(bk & m) - b2;
-    if (bx < 0 || bx >= d0 || by < 0 || by >= d1 || bz < 0 || bz >= d2) return;
-    const int64_t bit = ((int64_t)bx * d1 + by) * d2 + bz;
-    atomicOr(&bmap[bit >> 5], 1u << (bit & 31));
-}
-
-__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 __global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -305,22 +284,6 @@ vg_status build_level(vg_context* ctx, const double* d_xyz, const double* d_cov,
             out->kmin[a] = h_box[a];
             out->kmax[a] = h_box[3 + a];
         }
-        // 6. block occupancy bitmap over the key box (skipped beyond 2^27 blocks)
-        int64_t nbits = 1;
-        for (int a = 0; a < 3; ++a) {
-            out->bmin[a] = (out->kmin[a] + kKeyBias) >> kBlockShift;
-            out->bdim[a] = ((out->kmax[a] + kKeyBias) >> kBlockShift) - out->bmin[a] + 1;
-            nbits *= out->bdim[a];
-        }
-        if (nbits <= (1ll << 27)) {
-            const int64_t words = (nbits + 31) / 32;
-            VG_HIP(hipMalloc(&out->bmap, sizeof(uint32_t) * (size_t)words));
-            k_fill_u32<<<grid_of(words), 256, 0, st>>>(out->bmap, words, 0u);
-            VG_HIP(hipGetLastError());
-            k_block_bitmap<<<grid_of(NB), 256, 0, st>>>(ublocks, NB, out->bmin[0], out->bmin[1], out->bmin[2],
-                                                        out->bdim[0], out->bdim[1], out->bdim[2], out->bmap);
-            VG_HIP(hipGetLastError());
-        }
     } else {
         out->log2cap = 6;
         VG_HIP(hipMalloc(&out->slots, sizeof(uint64_t) * 2 * 64));
@@ -367,7 +330,6 @@ void free_level(Level* lv) {
     if (lv->keys) (void)hipFree(lv->keys);
     if (lv->counts) (void)hipFree(lv->counts);
     if (lv->lex2rec) (void)hipFree(lv->lex2rec);
-    if (lv->bmap) (void)hipFree(lv->bmap);
     *lv = Level{};
 }
 

@@ -14,7 +14,8 @@ import threading
 import torch  # noqa: F401  (must precede loading the HIP library)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvgicp.so")
+# the in-tree build; VGICP_LIBRARY names another build of the same sources
+LIB_PATH = os.environ.get("VGICP_LIBRARY") or os.path.join(_HERE, "libvgicp.so")
 
 VG_OK = 0
 STATUS = {

@@ -216,8 +216,10 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
                                               float dz, int32_t i, int32_t v, int32_t cl) {
     const int c = cl >> 2, l = cl & 3;
     const LevelDesc& lv = Fp->lv[l];
-    const auto r4 = gbl(reinterpret_cast<const f32x4*>(lv.rec32 + (int64_t)v * kRec32));
-    const f32x4 q0 = r4[0], q1 = r4[1], q2 = r4[2], q3 = r4[3];
+    const float* rec = lv.rec32 + (int64_t)v * kRec32;
+    const f32x4 q0 = *gbl(reinterpret_cast<const f32x4*>(rec));
+    const auto c2 = gbl(reinterpret_cast<const f64x2*>(rec + 4));
+    const f64x2 cva = c2[0], cvb = c2[1], cvc = c2[2];
     double S[6];
     point_S<kC32>(Fp, (int64_t)i, n_pad, P, R, S);
     float jf[3], z[3];
@@ -228,12 +230,12 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
         z[a] = sh.za[3 * c + a] + fmaf(R[3 * a + 2], dz, fmaf(R[3 * a + 1], dy, R[3 * a] * dx));
     }
     double M[6], W64[6];
-    M[0] = ((double)q0.w + (double)q2.y) + S[0];
-    M[1] = ((double)q1.x + (double)q2.z) + S[1];
-    M[2] = ((double)q1.y + (double)q2.w) + S[2];
-    M[3] = ((double)q1.z + (double)q3.x) + S[3];
-    M[4] = ((double)q1.w + (double)q3.y) + S[4];
-    M[5] = ((double)q2.x + (double)q3.z) + S[5];
+    M[0] = cva.x + S[0];
+    M[1] = cva.y + S[1];
+    M[2] = cvb.x + S[2];
+    M[3] = cvb.y + S[3];
+    M[4] = cvc.x + S[4];
+    M[5] = cvc.y + S[5];
     sym3_inverse(M, W64);
     float W[6], d[3];
 #pragma unroll
@@ -574,20 +576,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 if constexpr (PREC == kC32) {
                     // the voxel record's loads are issued before the covariance's (first
                     // hit only), so the two round trips overlap
-                    const auto r4 = gbl(reinterpret_cast<const f32x4*>(lv.rec32 + (int64_t)v * kRec32));
-                    const f32x4 q0 = r4[0], q1 = r4[1], q2 = r4[2], q3 = r4[3];
+                    const float* rec = lv.rec32 + (int64_t)v * kRec32;
+                    const f32x4 q0 = *gbl(reinterpret_cast<const f32x4*>(rec));
+                    const auto c2 = gbl(reinterpret_cast<const f64x2*>(rec + 4));
+                    const f64x2 cva = c2[0], cvb = c2[1], cvc = c2[2];
                     if (!haveS) {
                         point_S<PREC>(Fp, i, n_pad, P, R, S);
                         haveS = true;
                     }
                     mv[0] = q0.x; mv[1] = q0.y; mv[2] = q0.z;
                     double M[6], W64[6];
-                    M[0] = ((double)q0.w + (double)q2.y) + S[0];
-                    M[1] = ((double)q1.x + (double)q2.z) + S[1];
-                    M[2] = ((double)q1.y + (double)q2.w) + S[2];
-                    M[3] = ((double)q1.z + (double)q3.x) + S[3];
-                    M[4] = ((double)q1.w + (double)q3.y) + S[4];
-                    M[5] = ((double)q2.x + (double)q3.z) + S[5];
+                    M[0] = cva.x + S[0];
+                    M[1] = cva.y + S[1];
+                    M[2] = cvb.x + S[2];
+                    M[3] = cvb.y + S[3];
+                    M[4] = cvc.x + S[4];
+                    M[5] = cvc.y + S[5];
                     sym3_inverse(M, W64);
 #pragma unroll
                     for (int k = 0; k < 6; ++k) W[k] = (float)W64[k];

@@ -26,7 +26,7 @@ constexpr uint64_t kEmpty = ~0ull;      // empty block-table entry
 constexpr int kRow = 32;                // partial row: 28 terms + 4 inlier counts
 constexpr int kTerms = 28;              // e, 21 upper-triangular H, 6 b
 constexpr int kMaxTileChunks = 128;     // at most 8192 points per tile
-constexpr int kRec32 = 16;              // floats per compensated voxel record (64 B)
+constexpr int kRec32 = 16;              // floats per compensated voxel record (64 B: 4 FP32 + 6 FP64)
 constexpr int kRecN = 12;               // floats per absolute-FP32 voxel record
 constexpr int kRec64 = 10;              // doubles per FP64 voxel record
 constexpr int kOutRow = 43;             // e, H (36), b (6)
@@ -41,7 +41,7 @@ enum Prec { kN32 = VG_FP32, kC32 = VG_FP32_COMPENSATED, kF64 = VG_FP64 };
 struct LevelDesc {
     const uint64_t* slots;   // 2^log2cap block entries of two words:
                              //   [(36-bit block key << 28) | first record, 64-bit occupancy]
-    const float* rec32;      // V x 16: mean - voxel centre (3), cov hi (6), cov lo (6), count
+    const float* rec32;      // V x 16 floats (64 B): mean - voxel centre (3 FP32), count (FP32), cov (6 FP64)
     const float* recN;       // V x 12: FP32 absolute mean (3), cov (6), pad
     const double* rec64;     // V x 10: absolute mean (3), cov (6), pad
     uint32_t log2cap;

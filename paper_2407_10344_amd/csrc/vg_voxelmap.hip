@@ -64,6 +64,7 @@ __global__ void k_level_stats(const double* __restrict__ xyz, const double* __re
     const int64_t w = pos[v];
     double* r64 = rec64 + kRec64 * w;
     float* r32 = rec32 + kRec32 * w;
+    double* r32c = reinterpret_cast<double*>(r32 + 4);   // 8-byte aligned: records are 64 B
     float* rN = recN + kRecN * w;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -72,16 +73,14 @@ __global__ void k_level_stats(const double* __restrict__ xyz, const double* __re
         r32[a] = (float)(m[a] - centre);
         rN[a] = (float)m[a];
     }
+    r32[3] = (float)cnt;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        const float hi = (float)m[3 + k];
         r64[3 + k] = m[3 + k];
-        r32[3 + k] = hi;                                // covariance, high part
-        r32[9 + k] = (float)(m[3 + k] - (double)hi);    // covariance, low part
-        rN[3 + k] = hi;
+        r32c[k] = m[3 + k];                             // covariance, FP64
+        rN[3 + k] = (float)m[3 + k];
     }
     r64[9] = 0.0;
-    r32[15] = (float)cnt;
     rN[9] = 0.f;
     rN[10] = 0.f;
     rN[11] = 0.f;

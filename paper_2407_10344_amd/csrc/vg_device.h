@@ -37,9 +37,16 @@ __host__ __device__ __forceinline__ void unpack_key(uint64_t p, int64_t k[3]) {
     k[2] = (int64_t)(p & m) - kKeyBias;
 }
 
-// Multiplicative (Fibonacci) hashing of the packed key to a slot.
-__host__ __device__ __forceinline__ uint32_t slot_of(uint64_t key, uint32_t log2cap) {
-    return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - log2cap));
+// Slot of a block (block coordinates bx, by, bz, 12 bits each): the top bits
+// of three 32-bit multiplicative hashes, combined with XOR (32-bit arithmetic
+// only).  The block key packs the same coordinates into 36 bits.
+__host__ __device__ __forceinline__ uint32_t slot_of_block(uint32_t bx, uint32_t by, uint32_t bz, uint32_t log2cap) {
+    return ((bx * 0x9E3779B1u) ^ (by * 0x85EBCA77u) ^ (bz * 0xC2B2AE3Du)) >> (32u - log2cap);
+}
+__host__ __device__ __forceinline__ uint32_t slot_of(uint64_t bk, uint32_t log2cap) {
+    const uint32_t m = (1u << kBlockBits) - 1u;
+    return slot_of_block((uint32_t)(bk >> (2 * kBlockBits)) & m, (uint32_t)(bk >> kBlockBits) & m, (uint32_t)bk & m,
+                         log2cap);
 }
 
 // Sparse-block voxel lookup.  Voxels are grouped in 4 x 4 x 4 blocks; a hash
@@ -59,19 +66,27 @@ __host__ __device__ __forceinline__ uint64_t block_key(uint64_t ux, uint64_t uy,
 }
 
 // Record index of relative key (kx, ky, kz) (each in [-8192, 8191]), or -1.
-__device__ __forceinline__ int32_t lookup(const uint64_t* __restrict__ slots, uint32_t log2cap, int64_t kx,
-                                          int64_t ky, int64_t kz) {
-    const uint64_t ux = (uint64_t)(kx + kKeyBias), uy = (uint64_t)(ky + kKeyBias), uz = (uint64_t)(kz + kKeyBias);
-    const uint64_t bk = block_key(ux, uy, uz);
-    const uint64_t bit = 1ull << block_local(ux, uy, uz);
+// 32-bit arithmetic except the 36-bit block key comparison.
+__device__ __forceinline__ int32_t lookup(const uint64_t* __restrict__ slots, uint32_t log2cap, int32_t kx,
+                                          int32_t ky, int32_t kz) {
+    const uint32_t ux = (uint32_t)(kx + kKeyBias), uy = (uint32_t)(ky + kKeyBias), uz = (uint32_t)(kz + kKeyBias);
+    const uint32_t bx = ux >> kBlockShift, by = uy >> kBlockShift, bz = uz >> kBlockShift;
+    const uint64_t bk = ((uint64_t)bx << (2 * kBlockBits)) | (uint64_t)((by << kBlockBits) | bz);
+    const uint32_t local = (ux & 1u) | ((uy & 1u) << 1) | ((uz & 1u) << 2) | ((ux & 2u) << 2) | ((uy & 2u) << 3) |
+                           ((uz & 2u) << 4);
     const uint32_t mask = (1u << log2cap) - 1u;
-    uint32_t h = slot_of(bk, log2cap);
+    uint32_t h = slot_of_block(bx, by, bz, log2cap);
     for (uint32_t it = 0; it <= mask; ++it) {
         const u64x2 e = *gbl(reinterpret_cast<const u64x2*>(slots + 2 * (uint64_t)h));
         if (e.x == kEmpty) return -1;
         if ((e.x >> kBaseBits) == bk) {
-            if (!(e.y & bit)) return -1;
-            return (int32_t)(e.x & kBaseMask) + __popcll(e.y & (bit - 1));
+            // occupancy bit and the number of occupied voxels below it, on 32-bit halves
+            const uint32_t lo = (uint32_t)e.y, hi = (uint32_t)(e.y >> 32);
+            const uint32_t word = local < 32 ? lo : hi;
+            if (!((word >> (local & 31)) & 1u)) return -1;
+            const uint32_t below = local < 32 ? __popc(lo & ((1u << local) - 1u))
+                                              : __popc(lo) + __popc(hi & ((1u << (local - 32)) - 1u));
+            return (int32_t)(e.x & kBaseMask) + (int32_t)below;
         }
         h = (h + 1u) & mask;
     }

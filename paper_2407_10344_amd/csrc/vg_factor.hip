@@ -423,10 +423,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     const LevelDesc& lv = Fp->lv[l];
                     int32_t v = -1;
                     if (vis) {
-                        int64_t kq[3];
+                        int32_t kq[3];
 #pragma unroll
                         for (int a = 0; a < 3; ++a)
-                            kq[a] = (int64_t)sh.kb[3 * c + a] * lv.scale + (int64_t)floorf(yl[a] * lv.inv_r);
+                            kq[a] = sh.kb[3 * c + a] * lv.scale + (int32_t)floorf(yl[a] * lv.inv_r);
                         if (kq[0] >= lv.kmin[0] && kq[0] <= lv.kmax[0] && kq[1] >= lv.kmin[1] && kq[1] <= lv.kmax[1] &&
                             kq[2] >= lv.kmin[2] && kq[2] <= lv.kmax[2])
                             v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
@@ -567,7 +567,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 if (!(kq[0] >= lv.kmin[0] && kq[0] <= lv.kmax[0] && kq[1] >= lv.kmin[1] && kq[1] <= lv.kmax[1] &&
                       kq[2] >= lv.kmin[2] && kq[2] <= lv.kmax[2]))
                     continue;
-                const int32_t v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
+                const int32_t v = lookup(lv.slots, lv.log2cap, (int32_t)kq[0], (int32_t)kq[1], (int32_t)kq[2]);
                 if (v < 0) continue;
                 inl[l] += 1;
                 if constexpr (MODE == kCount) continue;
@@ -922,7 +922,7 @@ __global__ void k_correspondences(const FactorDesc* __restrict__ fac, int64_t fa
         int32_t fnd;
         if (!vis) fnd = -1;
         else if (!(key_in_range(kq[0]) && key_in_range(kq[1]) && key_in_range(kq[2]))) fnd = 0;
-        else fnd = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]) >= 0 ? 1 : 0;
+        else fnd = lookup(lv.slots, lv.log2cap, (int32_t)kq[0], (int32_t)kq[1], (int32_t)kq[2]) >= 0 ? 1 : 0;
         found[row * L + l] = fnd;
     }
 }

@@ -567,6 +567,8 @@ void fill_factor(vg_batch* b, int64_t f, const double* viewpoints) {
         q.rec64 = lv.rec64;
         q.log2cap = lv.log2cap;
         q.scale = (int32_t)std::llround(rmax / lv.r);
+        q.log2scale = 0;
+        while ((1 << q.log2scale) < q.scale) ++q.log2scale;
         q.r = (float)lv.r;
         q.inv_r = (float)(1.0 / lv.r);
         q.r64 = lv.r;
@@ -575,6 +577,9 @@ void fill_factor(vg_batch* b, int64_t f, const double* viewpoints) {
             q.K0[a] = lv.K0[a];
             q.kmin[a] = lv.kmin[a];
             q.kmax[a] = lv.kmax[a];
+            const bool empty = lv.kmin[a] > lv.kmax[a];
+            q.kbox0[a] = empty ? 0 : lv.kmin[a];
+            q.kboxw[a] = empty ? 0u : (uint32_t)(lv.kmax[a] - lv.kmin[a]);
         }
     }
     b->h_fac[f] = d;

@@ -37,11 +37,12 @@ __host__ __device__ __forceinline__ void unpack_key(uint64_t p, int64_t k[3]) {
     k[2] = (int64_t)(p & m) - kKeyBias;
 }
 
-// Slot of a block (block coordinates bx, by, bz, 12 bits each): the top bits
-// of three 32-bit multiplicative hashes, combined with XOR (32-bit arithmetic
-// only).  The block key packs the same coordinates into 36 bits.
+// Slot of a block (block coordinates bx, by, bz, 12 bits each): Fibonacci
+// hashing (the top bits of one 32-bit product with the golden-ratio constant)
+// of the coordinates folded into one word.  The block key packs the same
+// coordinates into 36 bits.
 __host__ __device__ __forceinline__ uint32_t slot_of_block(uint32_t bx, uint32_t by, uint32_t bz, uint32_t log2cap) {
-    return ((bx * 0x9E3779B1u) ^ (by * 0x85EBCA77u) ^ (bz * 0xC2B2AE3Du)) >> (32u - log2cap);
+    return (((bx << 20) ^ (by << 10) ^ bz) * 0x9E3779B1u) >> (32u - log2cap);
 }
 __host__ __device__ __forceinline__ uint32_t slot_of(uint64_t bk, uint32_t log2cap) {
     const uint32_t m = (1u << kBlockBits) - 1u;
@@ -53,12 +54,11 @@ __host__ __device__ __forceinline__ uint32_t slot_of(uint64_t bk, uint32_t log2c
 // table (open addressing, linear probing, load factor <= 1/4) maps each
 // occupied block to one 16-byte entry: (block key << 28 | index of the block's
 // first record) and a 64-bit occupancy mask.  Records are stored block by
-// block, in Morton order inside a block, so a voxel's record index is
-// first + popcount(mask below its bit).  Neighbouring points share block
-// entries and read neighbouring records.
+// block, x fastest inside a block (bit x + 4 y + 16 z), so a voxel's record
+// index is first + popcount(mask below its bit).  Neighbouring points share
+// block entries and read neighbouring records.
 __host__ __device__ __forceinline__ uint32_t block_local(uint64_t ux, uint64_t uy, uint64_t uz) {
-    return (uint32_t)((ux & 1) | ((uy & 1) << 1) | ((uz & 1) << 2) | (((ux >> 1) & 1) << 3) |
-                      (((uy >> 1) & 1) << 4) | (((uz >> 1) & 1) << 5));
+    return (uint32_t)((ux & 3) | ((uy & 3) << 2) | ((uz & 3) << 4));
 }
 
 __host__ __device__ __forceinline__ uint64_t block_key(uint64_t ux, uint64_t uy, uint64_t uz) {
@@ -66,26 +66,25 @@ __host__ __device__ __forceinline__ uint64_t block_key(uint64_t ux, uint64_t uy,
 }
 
 // Record index of relative key (kx, ky, kz) (each in [-8192, 8191]), or -1.
-// 32-bit arithmetic except the 36-bit block key comparison.
+// 32-bit arithmetic except the 36-bit block key; the occupancy test and the
+// popcount below the voxel's bit take no branch on which half holds the bit.
 __device__ __forceinline__ int32_t lookup(const uint64_t* __restrict__ slots, uint32_t log2cap, int32_t kx,
                                           int32_t ky, int32_t kz) {
     const uint32_t ux = (uint32_t)(kx + kKeyBias), uy = (uint32_t)(ky + kKeyBias), uz = (uint32_t)(kz + kKeyBias);
     const uint32_t bx = ux >> kBlockShift, by = uy >> kBlockShift, bz = uz >> kBlockShift;
     const uint64_t bk = ((uint64_t)bx << (2 * kBlockBits)) | (uint64_t)((by << kBlockBits) | bz);
-    const uint32_t local = (ux & 1u) | ((uy & 1u) << 1) | ((uz & 1u) << 2) | ((ux & 2u) << 2) | ((uy & 2u) << 3) |
-                           ((uz & 2u) << 4);
+    const uint32_t local = (ux & 3u) | ((uy & 3u) << 2) | ((uz & 3u) << 4);
+    const bool upper = local >= 32u;
+    const uint32_t below_mask = (1u << (local & 31u)) - 1u;
     const uint32_t mask = (1u << log2cap) - 1u;
     uint32_t h = slot_of_block(bx, by, bz, log2cap);
     for (uint32_t it = 0; it <= mask; ++it) {
         const u64x2 e = *gbl(reinterpret_cast<const u64x2*>(slots + 2 * (uint64_t)h));
         if (e.x == kEmpty) return -1;
         if ((e.x >> kBaseBits) == bk) {
-            // occupancy bit and the number of occupied voxels below it, on 32-bit halves
             const uint32_t lo = (uint32_t)e.y, hi = (uint32_t)(e.y >> 32);
-            const uint32_t word = local < 32 ? lo : hi;
-            if (!((word >> (local & 31)) & 1u)) return -1;
-            const uint32_t below = local < 32 ? __popc(lo & ((1u << local) - 1u))
-                                              : __popc(lo) + __popc(hi & ((1u << (local - 32)) - 1u));
+            if (!(((upper ? hi : lo) >> (local & 31u)) & 1u)) return -1;
+            const uint32_t below = __popc(upper ? lo : (lo & below_mask)) + __popc(upper ? (hi & below_mask) : 0u);
             return (int32_t)(e.x & kBaseMask) + (int32_t)below;
         }
         h = (h + 1u) & mask;
@@ -105,12 +104,21 @@ __device__ __forceinline__ double recip(double x) {
     return fma(r, fma(-x, r, 1.0), r);
 }
 
+// floor(x) as an int32 in one instruction (v_cvt_flr_i32_f32; equal to
+// (int32_t)floorf(x) for finite x in the int32 range, which holds for every
+// chunk-relative key position the kernels form).
+__device__ __forceinline__ int32_t floor_i32(float x) {
+    int32_t r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 // Position of a point relative to its chunk anchor's coarse voxel corner, in
 // FP32, with an explicit FMA order so every kernel that derives voxel keys
 // from it gets identical bits.
 __device__ __forceinline__ float chunk_pos32(float frac, float r0, float r1, float r2, float dx, float dy,
                                              float dz) {
-    return frac + fmaf(r2, dz, fmaf(r1, dy, r0 * dx));
+    return fmaf(r2, dz, fmaf(r1, dy, fmaf(r0, dx, frac)));
 }
 
 // Per-chunk FP64 anchor transform for axis i: ya = (R a + t)_i split into the

@@ -128,6 +128,18 @@ __device__ __forceinline__ void add_lin_terms(A& acc, const T d[3], const T w[6]
     acc.add(27, -u[2]);
 }
 
+// The fields of one level that the probe reads for every chunk.
+struct ProbeLevel {
+    const uint64_t* slots;
+    uint32_t log2cap, log2scale;
+    float inv_r;
+    int32_t kbox0[3];
+    uint32_t kboxw[3];
+    __device__ __forceinline__ explicit ProbeLevel(const LevelDesc& lv)
+        : slots(lv.slots), log2cap(lv.log2cap), log2scale((uint32_t)lv.log2scale), inv_r(lv.inv_r),
+          kbox0{lv.kbox0[0], lv.kbox0[1], lv.kbox0[2]}, kboxw{lv.kboxw[0], lv.kboxw[1], lv.kboxw[2]} {}
+};
+
 // Per-tile chunk data in LDS.  At 4 waves per SIMD a CU holds at most 16
 // waves, so even one-wave workgroups need at most 16 x 9 KB of the 160 KB.
 struct TileShared {
@@ -222,11 +234,12 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
     const f64x2 cva = c2[0], cvb = c2[1], cvc = c2[2];
     double S[6];
     point_S<kC32>(Fp, (int64_t)i, n_pad, P, R, S);
-    float jf[3], z[3];
+    int32_t jk[3];
+    float z[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float yl = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
-        jf[a] = floorf(yl * lv.inv_r);
+        jk[a] = floor_i32(yl * lv.inv_r);
         z[a] = sh.za[3 * c + a] + fmaf(R[3 * a + 2], dz, fmaf(R[3 * a + 1], dy, R[3 * a] * dx));
     }
     double M[6], W64[6];
@@ -245,7 +258,7 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double y64 = sh.frac[3 * c + a] + (P[3 * a] * ddx + P[3 * a + 1] * ddy + P[3 * a + 2] * ddz);
-        d[a] = (float)((double)mv[a] - (y64 - ((double)jf[a] + 0.5) * lv.r64));
+        d[a] = (float)((double)mv[a] - (y64 - ((double)jk[a] + 0.5) * lv.r64));
     }
     add_lin_terms(acc, d, W, z);
 }
@@ -281,7 +294,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
     __shared__ double s_red[NW][kRow];
     __shared__ int32_t s_tile;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // wave index as a uniform (scalar) value, so chunk indices and per-chunk LDS
+    // addresses are computed once per wave, not per lane
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // XCD-aware work distribution: the tiles are split into kParts partitions with
     // one counter each; workgroups are dispatched round-robin over the XCDs, so
     // workgroup b starts on partition b % kParts, i.e. on its XCD's partition.
@@ -388,6 +403,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
 
         int q_head = 0, q_count = 0;   // this wave's hit queue (wave-uniform)
 
+        // the first level's probe constants, loaded once per tile (uniform)
+        const ProbeLevel pl0(Fp->lv[0]);
         // each wave walks chunks wave, wave + NW, ...; the next chunk's point is
         // loaded before the current one is processed, so its latency overlaps
         RawPoint<PREC> nxt;
@@ -413,24 +430,27 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     yl[a] = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
                 bool vis = live;
                 if (live && validate) {
-                    const float sv = (sh.vc[3 * c + 0] + dx) * Fp->nrm[i] + (sh.vc[3 * c + 1] + dy) * Fp->nrm[n_pad + i] +
-                                     (sh.vc[3 * c + 2] + dz) * Fp->nrm[2 * n_pad + i];
+                    const auto Nv = gbl(Fp->nrm);
+                    const float sv = (sh.vc[3 * c + 0] + dx) * Nv[i] + (sh.vc[3 * c + 1] + dy) * Nv[n_pad + i] +
+                                     (sh.vc[3 * c + 2] + dz) * Nv[2 * n_pad + i];
                     vis = !(sv > 0.0f);
                 }
 #pragma unroll
                 for (int l = 0; l < kMaxLevels; ++l) {
                     if (l >= L) break;
                     const LevelDesc& lv = Fp->lv[l];
+                    const ProbeLevel pl = l == 0 ? pl0 : ProbeLevel(lv);
                     int32_t v = -1;
-                    if (vis) {
-                        int32_t kq[3];
+                    // key (coarse anchor key times the level ratio, a shift) and the
+                    // bounding-box test as one unsigned compare per axis, no branches
+                    int32_t kq[3];
+                    bool in = vis;
 #pragma unroll
-                        for (int a = 0; a < 3; ++a)
-                            kq[a] = sh.kb[3 * c + a] * lv.scale + (int32_t)floorf(yl[a] * lv.inv_r);
-                        if (kq[0] >= lv.kmin[0] && kq[0] <= lv.kmax[0] && kq[1] >= lv.kmin[1] && kq[1] <= lv.kmax[1] &&
-                            kq[2] >= lv.kmin[2] && kq[2] <= lv.kmax[2])
-                            v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
+                    for (int a = 0; a < 3; ++a) {
+                        kq[a] = (int32_t)((uint32_t)sh.kb[3 * c + a] << pl.log2scale) + floor_i32(yl[a] * pl.inv_r);
+                        in &= (uint32_t)(kq[a] - pl.kbox0[a]) <= pl.kboxw[a];
                     }
+                    if (in) v = lookup(pl.slots, pl.log2cap, kq[0], kq[1], kq[2]);
                     const bool hit = v >= 0;
                     inl[l] += hit ? 1 : 0;
                     const uint64_t mask = __ballot(hit);
@@ -479,8 +499,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 x[1] = dy;
                 x[2] = dz;
                 if (validate) {
-                    const float s = (sh.vc[3 * c + 0] + dx) * Fp->nrm[i] + (sh.vc[3 * c + 1] + dy) * Fp->nrm[n_pad + i] +
-                                    (sh.vc[3 * c + 2] + dz) * Fp->nrm[2 * n_pad + i];
+                    const auto Nv = gbl(Fp->nrm);
+                    const float s = (sh.vc[3 * c + 0] + dx) * Nv[i] + (sh.vc[3 * c + 1] + dy) * Nv[n_pad + i] +
+                                    (sh.vc[3 * c + 2] + dz) * Nv[2 * n_pad + i];
                     vis = !(s > 0.0f);
                 }
             } else if constexpr (PREC == kN32) {
@@ -492,8 +513,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     yl[a] = z[a] + tt[a];
                 }
                 if (validate) {
-                    const float s = (x[0] - (float)cs[0]) * Fp->nrm[i] + (x[1] - (float)cs[1]) * Fp->nrm[n_pad + i] +
-                                    (x[2] - (float)cs[2]) * Fp->nrm[2 * n_pad + i];
+                    const auto Nv = gbl(Fp->nrm);
+                    const float s = (x[0] - (float)cs[0]) * Nv[i] + (x[1] - (float)cs[1]) * Nv[n_pad + i] +
+                                    (x[2] - (float)cs[2]) * Nv[2 * n_pad + i];
                     vis = !(s > 0.0f);
                 }
             } else {
@@ -538,36 +560,32 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
             for (int l = 0; l < kMaxLevels; ++l) {
                 if (l >= L) break;
                 const LevelDesc& lv = Fp->lv[l];
-                int64_t kq[3];
-                float jf[3];
+                // relative key; a key outside the level's key bounding box (which also
+                // covers keys outside the packable range) has no voxel and is not probed
+                int32_t kq[3];
+                bool in = true;
+                int32_t jk[3];
                 T pc[3];   // absolute position (kN32, kF64)
                 if constexpr (PREC == kC32) {
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        jf[a] = floorf(yl[a] * lv.inv_r);
-                        kq[a] = (int64_t)sh.kb[3 * c + a] * lv.scale + (int64_t)jf[a];
-                    }
-                } else if constexpr (PREC == kN32) {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const float q = floorf(yl[a] * lv.inv_r);
-                        kq[a] = (int64_t)q - lv.K0[a];
-                        pc[a] = yl[a];
+                        jk[a] = floor_i32(yl[a] * lv.inv_r);
+                        kq[a] = (int32_t)((uint32_t)sh.kb[3 * c + a] << lv.log2scale) + jk[a];
+                        in &= (uint32_t)(kq[a] - lv.kbox0[a]) <= lv.kboxw[a];
                     }
                 } else {
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        const double q = floor(yl[a] * lv.inv_r64);
-                        kq[a] = (int64_t)q - lv.K0[a];
+                        int64_t k;
+                        if constexpr (PREC == kN32) k = (int64_t)floorf(yl[a] * lv.inv_r) - lv.K0[a];
+                        else k = (int64_t)floor(yl[a] * lv.inv_r64) - lv.K0[a];
+                        in &= (k >= lv.kmin[a]) & (k <= lv.kmax[a]);
+                        kq[a] = (int32_t)k;
                         pc[a] = yl[a];
                     }
                 }
-                // outside the level's key bounding box (also covers keys outside the
-                // packable range): no voxel, no probe
-                if (!(kq[0] >= lv.kmin[0] && kq[0] <= lv.kmax[0] && kq[1] >= lv.kmin[1] && kq[1] <= lv.kmax[1] &&
-                      kq[2] >= lv.kmin[2] && kq[2] <= lv.kmax[2]))
-                    continue;
-                const int32_t v = lookup(lv.slots, lv.log2cap, (int32_t)kq[0], (int32_t)kq[1], (int32_t)kq[2]);
+                if (!in) continue;
+                const int32_t v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
                 if (v < 0) continue;
                 inl[l] += 1;
                 if constexpr (MODE == kCount) continue;
@@ -624,7 +642,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         const double y64 = sh.frac[3 * c + a] + (P[3 * a] * ddx + P[3 * a + 1] * ddy + P[3 * a + 2] * ddz);
-                        d[a] = (float)((double)mv[a] - (y64 - ((double)jf[a] + 0.5) * lv.r64));
+                        d[a] = (float)((double)mv[a] - (y64 - ((double)jk[a] + 0.5) * lv.r64));
                     }
                 } else {
 #pragma unroll
@@ -911,7 +929,7 @@ __global__ void k_correspondences(const FactorDesc* __restrict__ fac, int64_t fa
         int64_t kq[3];
         for (int q = 0; q < 3; ++q) {
             if constexpr (PREC == kC32) {
-                kq[q] = (int64_t)kb[q] * lv.scale + (int64_t)floorf(yl[q] * lv.inv_r);
+                kq[q] = (int64_t)kb[q] * lv.scale + (int64_t)floor_i32(yl[q] * lv.inv_r);
             } else if constexpr (PREC == kN32) {
                 kq[q] = (int64_t)floorf(yl[q] * lv.inv_r) - lv.K0[q];
             } else {

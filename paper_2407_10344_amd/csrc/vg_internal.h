@@ -46,10 +46,13 @@ struct LevelDesc {
     const double* rec64;     // V x 10: absolute mean (3), cov (6), pad
     uint32_t log2cap;
     int32_t scale;           // r_coarsest / r_l (power of two)
+    int32_t log2scale;       // log2 of scale
     float r, inv_r;
     double r64, inv_r64;
     int64_t K0[3];           // absolute key of the map origin at this level
     int32_t kmin[3], kmax[3];// bounding box of the level's relative keys (empty: min > max)
+    int32_t kbox0[3];        // the same box as kbox0 + [0, kboxw] (empty level: the single key 0)
+    uint32_t kboxw[3];
 };
 
 // One factor: a source cloud (internal Morton order) matched into a target map.

@@ -121,16 +121,17 @@ __device__ __forceinline__ float chunk_pos32(float frac, float r0, float r1, flo
     return fmaf(r2, dz, fmaf(r1, dy, fmaf(r0, dx, frac)));
 }
 
-// Per-chunk FP64 anchor transform for axis i: ya = (R a + t)_i split into the
-// coarse voxel key (relative to the map origin, clamped far outside the key
-// range) and the remainder inside that voxel.  Shared by every kernel that
+// Per-chunk FP64 anchor transform for axis i: ya = (R a + t)_i (returned)
+// split into the coarse voxel key (relative to the map origin, clamped far
+// outside the key range) and the remainder inside that voxel.  Shared by every kernel that
 // derives keys from chunk anchors so they agree bit for bit.
-__device__ __forceinline__ void anchor_split(const double* __restrict__ P, const double a[3], int i, double r_top,
-                                             double inv_r_top, int64_t K0_top, double* frac, int32_t* kb) {
+__device__ __forceinline__ double anchor_split(const double* __restrict__ P, const double a[3], int i, double r_top,
+                                               double inv_r_top, int64_t K0_top, double* frac, int32_t* kb) {
     const double ya = fma(P[3 * i + 2], a[2], fma(P[3 * i + 1], a[1], P[3 * i] * a[0])) + P[9 + i];
     const double k = floor(ya * inv_r_top);
     *frac = ya - k * r_top;
     *kb = (int32_t)fmin(fmax(k - (double)K0_top, -1048576.0), 1048576.0);
+    return ya;
 }
 
 // Inverse of a symmetric 3x3 matrix m = [a b c; b d e; c e f] via its adjugate.

@@ -148,6 +148,9 @@ struct TileShared {
     int32_t kb[kMaxTileChunks * 3];    // coarse relative key of the anchor
     float za[kMaxTileChunks * 3];      // R (anchor - o_s)
     float vc[kMaxTileChunks * 3];      // anchor - T^-1 c (surface validation)
+    int32_t live[kMaxTileChunks];      // the chunks the waves walk, in chunk order
+    int32_t nlive;
+    uint8_t reach[kMaxTileChunks];     // chunk can reach a level's key box
 };
 
 // Per-wave queue of (point, level) hits of the compacted linearization: the
@@ -288,6 +291,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
     constexpr bool KAHAN = KH && (PREC == kC32);
     constexpr int NT = (MODE == kLin) ? kTerms : (MODE == kBwd ? 6 : 1);
     constexpr bool CMP = (MODE == kLin && PREC == kC32);   // compacted hits
+    // chunks that cannot reach any level's key box are skipped (not in the
+    // backward pass, which writes a gradient row for every point)
+    constexpr bool SKIP = (PREC == kC32 && MODE != kBwd);
     __shared__ TileShared sh;
     using QueueT = typename std::conditional<CMP, HitQueue, int32_t>::type;
     __shared__ QueueT s_q[CMP ? NW : 1];
@@ -376,11 +382,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 const double a0 = a[0], a1 = a[1], a2 = a[2];
                 const double o0 = a0 - Fp->src_origin[0], o1 = a1 - Fp->src_origin[1], o2 = a2 - Fp->src_origin[2];
                 const double av[3] = {a0, a1, a2};
+                double ya[3];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     double fr;
                     int32_t kb;
-                    anchor_split(P, av, i, top.r64, top.inv_r64, top.K0[i], &fr, &kb);
+                    ya[i] = anchor_split(P, av, i, top.r64, top.inv_r64, top.K0[i], &fr, &kb);
                     sh.frac[3 * c + i] = fr;
                     sh.frac32[3 * c + i] = (float)fr;
                     sh.kb[3 * c + i] = kb;
@@ -391,9 +398,45 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     sh.vc[3 * c + 1] = (float)(a1 - cs[1]);
                     sh.vc[3 * c + 2] = (float)(a2 - cs[2]);
                 }
+                if constexpr (SKIP) {
+                    // Every point of the chunk lies within crad of the anchor (pose
+                    // rotations keep distances); a chunk whose ball misses the key box
+                    // of every level has no correspondence and is not walked.  The
+                    // margin (1e-3 m + 1e-5 relative) covers the FP32 key positions.
+                    const double rr = (double)gbl(Fp->crad)[tile.chunk0 + c] * (1.0 + 1e-5) + 1e-3;
+                    bool reach = false;
+                    for (int l = 0; l < L; ++l) {
+                        const LevelDesc& lv = Fp->lv[l];
+                        double d2 = 0.0;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            const double g = fmax(0.0, fmax(lv.blo[i] - ya[i], ya[i] - lv.bhi[i]));
+                            d2 += g * g;
+                        }
+                        reach |= d2 <= rr * rr;
+                    }
+                    sh.reach[c] = reach ? 1 : 0;
+                }
             }
             __syncthreads();
         }
+        // the list of chunks to walk (kept in chunk order)
+        if (wave == 0) {
+            int cnt = 0;
+            for (int base = 0; base < tile.nchunks; base += 64) {
+                const int c = base + lane;
+                bool keep = c < tile.nchunks;
+                if constexpr (SKIP) keep = keep && sh.reach[c];
+                const uint64_t m = __ballot(keep);
+                if (keep)
+                    sh.live[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = c;
+                cnt += __popcll(m);
+            }
+            if (lane == 0) sh.nlive = cnt;
+        }
+        __syncthreads();
+        const int nlive = __builtin_amdgcn_readfirstlane(sh.nlive);
         // ---------------------------------------------------------------- per-point work
         Acc<T, KAHAN, NT> acc;
         acc.zero();
@@ -405,18 +448,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
 
         // the first level's probe constants, loaded once per tile (uniform)
         const ProbeLevel pl0(Fp->lv[0]);
-        // each wave walks chunks wave, wave + NW, ...; the next chunk's point is
-        // loaded before the current one is processed, so its latency overlaps
+        // each wave walks list entries wave, wave + NW, ...; the next chunk's point
+        // is loaded before the current one is processed, so its latency overlaps
         RawPoint<PREC> nxt;
-        if (wave < tile.nchunks) {
-            const int64_t i0 = (int64_t)(tile.chunk0 + wave) * kChunk + lane;
+        if (wave < nlive) {
+            const int c0 = __builtin_amdgcn_readfirstlane(sh.live[wave]);
+            const int64_t i0 = (int64_t)(tile.chunk0 + c0) * kChunk + lane;
             if (i0 < n) load_point<PREC>(Fp, i0, n_pad, nxt);
         }
-        for (int c = wave; c < tile.nchunks; c += NW) {
+        for (int j = wave; j < nlive; j += NW) {
+            const int c = __builtin_amdgcn_readfirstlane(sh.live[j]);
             const int64_t i = (int64_t)(tile.chunk0 + c) * kChunk + lane;
             const RawPoint<PREC> cur = nxt;
-            if (c + NW < tile.nchunks) {
-                const int64_t in = i + (int64_t)NW * kChunk;
+            if (j + NW < nlive) {
+                const int cn = __builtin_amdgcn_readfirstlane(sh.live[j + NW]);
+                const int64_t in = (int64_t)(tile.chunk0 + cn) * kChunk + lane;
                 if (in < n) load_point<PREC>(Fp, in, n_pad, nxt);
             }
             if constexpr (CMP) {

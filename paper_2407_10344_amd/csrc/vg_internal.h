@@ -53,6 +53,7 @@ struct LevelDesc {
     int32_t kmin[3], kmax[3];// bounding box of the level's relative keys (empty: min > max)
     int32_t kbox0[3];        // the same box as kbox0 + [0, kboxw] (empty level: the single key 0)
     uint32_t kboxw[3];
+    double blo[3], bhi[3];   // the same box in metres, target frame (empty level: blo > bhi)
 };
 
 // One factor: a source cloud (internal Morton order) matched into a target map.
@@ -61,6 +62,7 @@ struct FactorDesc {
     const float* cov;        // 6 x n_pad SoA covariances
     const float* nrm;        // 3 x n_pad SoA normals or nullptr
     const double* anchor;    // n_chunks x 3 absolute anchors (source frame)
+    const float* crad;       // n_chunks: bound of the chunk's point offsets from its anchor (m)
     const float* axyz;       // 3 x n_pad absolute FP32 positions
     const double* xyz64;     // 3 x n_pad absolute FP64 positions
     const double* cov64;     // 6 x n_pad FP64 covariances
@@ -132,6 +134,7 @@ struct vg_source {
     float* cov = nullptr;
     float* nrm = nullptr;
     double* anchor = nullptr;
+    float* crad = nullptr;     // per chunk: bound of |offset from the anchor| (m)
     float* axyz = nullptr;
     double* xyz64 = nullptr;
     double* cov64 = nullptr;

@@ -430,6 +430,25 @@ __global__ void k_anchors(const double* __restrict__ xyz, const int32_t* __restr
     anchor[3 * c + 2] = s[2] * inv;
 }
 
+// Per chunk: an upper bound of the distance of its points from the anchor,
+// taken from the FP32 offsets the kernels read (FP64 squares, rounded up).
+__global__ void k_chunk_radius(const float* __restrict__ dxyz, int64_t n, int64_t n_pad, int64_t n_chunks,
+                               float* __restrict__ crad) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chunks) return;
+    const int64_t i0 = c * kChunk;
+    const int64_t i1 = (i0 + kChunk < n) ? i0 + kChunk : n;
+    double m = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const double x = dxyz[i], y = dxyz[n_pad + i], z = dxyz[2 * n_pad + i];
+        m = fmax(m, x * x + y * y + z * z);
+    }
+    const double r = sqrt(m);
+    float rf = (float)r;
+    if ((double)rf < r) rf = nextafterf(rf, INFINITY);
+    crad[c] = rf;
+}
+
 vg_status layout_source(vg_context* ctx, vg_source* s, const double* d_xyz, const double* d_cov,
                         const double* d_nrm) {
     hipStream_t st = ctx->stream;
@@ -459,6 +478,8 @@ vg_status layout_source(vg_context* ctx, vg_source* s, const double* d_xyz, cons
         if ((e = hipGetLastError()) != hipSuccess) break;
         k_layout<<<grid_of(n_pad), 256, 0, st>>>(d_xyz, d_cov, d_nrm, idx2, n, n_pad, s->dxyz, s->cov, s->nrm,
                                                  s->anchor, s->axyz, s->xyz64, s->cov64, s->nrm64, s->perm);
+        if ((e = hipGetLastError()) != hipSuccess) break;
+        k_chunk_radius<<<grid_of(s->n_chunks), 256, 0, st>>>(s->dxyz, n, n_pad, s->n_chunks, s->crad);
         if ((e = hipGetLastError()) != hipSuccess) break;
         e = hipStreamSynchronize(st);
     } while (0);
@@ -496,6 +517,9 @@ vg_status set_source_points(vg_context* ctx, vg_source* s, const void* d_xyz, in
     else
         k_set_points<double><<<grid_of(s->n), 256, 0, ctx->stream>>>((const double*)d_xyz, s->perm, s->anchor, s->n,
                                                                      s->n_pad, s->dxyz, s->axyz, s->xyz64);
+    VG_HIP(hipGetLastError());
+    // the offsets moved: so do the chunk bounds
+    k_chunk_radius<<<grid_of(s->n_chunks), 256, 0, ctx->stream>>>(s->dxyz, s->n, s->n_pad, s->n_chunks, s->crad);
     VG_HIP(hipGetLastError());
     return VG_OK;
 }

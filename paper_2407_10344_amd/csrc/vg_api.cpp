@@ -311,7 +311,7 @@ static void free_source(vg_source* s) {
     dfree(s->cov);
     dfree(s->nrm);
     dfree(s->anchor);
-    dfree(s->crad);
+    dfree(s->cbound);
     dfree(s->axyz);
     dfree(s->xyz64);
     dfree(s->cov64);
@@ -335,7 +335,7 @@ static vg_status make_source(vg_context* ctx, const double* d_xyz, const double*
         if ((st = dev_alloc(&s->dxyz, 3 * np)) != VG_OK) break;
         if ((st = dev_alloc(&s->cov, 6 * np)) != VG_OK) break;
         if ((st = dev_alloc(&s->anchor, 3 * s->n_chunks)) != VG_OK) break;
-        if ((st = dev_alloc(&s->crad, s->n_chunks)) != VG_OK) break;
+        if ((st = dev_alloc(&s->cbound, 8 * s->n_chunks)) != VG_OK) break;
         if ((st = dev_alloc(&s->axyz, 3 * np)) != VG_OK) break;
         if ((st = dev_alloc(&s->xyz64, 3 * np)) != VG_OK) break;
         if ((st = dev_alloc(&s->cov64, 6 * np)) != VG_OK) break;
@@ -547,7 +547,7 @@ void fill_factor(vg_batch* b, int64_t f, const double* viewpoints) {
     d.cov = s->cov;
     d.nrm = s->nrm;
     d.anchor = s->anchor;
-    d.crad = s->crad;
+    d.cbound = s->cbound;
     d.axyz = s->axyz;
     d.xyz64 = s->xyz64;
     d.cov64 = s->cov64;

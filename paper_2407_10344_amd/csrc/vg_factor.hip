@@ -399,21 +399,34 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     sh.vc[3 * c + 2] = (float)(a2 - cs[2]);
                 }
                 if constexpr (SKIP) {
-                    // Every point of the chunk lies within crad of the anchor (pose
-                    // rotations keep distances); a chunk whose ball misses the key box
-                    // of every level has no correspondence and is not walked.  The
-                    // margin (1e-3 m + 1e-5 relative) covers the FP32 key positions.
-                    const double rr = (double)gbl(Fp->crad)[tile.chunk0 + c] * (1.0 + 1e-5) + 1e-3;
+                    // Every point of the chunk lies in a ball around the anchor and in
+                    // a box of the source frame, both stored with the chunk.  In the
+                    // target frame the ball keeps its radius and the box is covered
+                    // by the axis-aligned box of half extents |R| h; a chunk whose
+                    // ball or box misses the key box of every level has no
+                    // correspondence and is not walked.  The margins (1e-3 m + 1e-5
+                    // relative) cover the FP32 key positions.
+                    const auto cb = gbl(Fp->cbound + 8 * (int64_t)(tile.chunk0 + c));
+                    const double rr = (double)cb[3] * (1.0 + 1e-5) + 1e-3;
+                    double yc[3], ex[3];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        yc[i] = ya[i] + (P[3 * i] * cb[0] + P[3 * i + 1] * cb[1] + P[3 * i + 2] * cb[2]);
+                        ex[i] = (fabs(P[3 * i]) * cb[4] + fabs(P[3 * i + 1]) * cb[5] + fabs(P[3 * i + 2]) * cb[6]) *
+                                    (1.0 + 1e-5) + 1e-3;
+                    }
                     bool reach = false;
                     for (int l = 0; l < L; ++l) {
                         const LevelDesc& lv = Fp->lv[l];
                         double d2 = 0.0;
+                        bool box = true;
 #pragma unroll
                         for (int i = 0; i < 3; ++i) {
                             const double g = fmax(0.0, fmax(lv.blo[i] - ya[i], ya[i] - lv.bhi[i]));
                             d2 += g * g;
+                            box = box && (yc[i] + ex[i] >= lv.blo[i]) && (yc[i] - ex[i] <= lv.bhi[i]);
                         }
-                        reach |= d2 <= rr * rr;
+                        reach |= (d2 <= rr * rr) && box;
                     }
                     sh.reach[c] = reach ? 1 : 0;
                 }

@@ -62,7 +62,8 @@ struct FactorDesc {
     const float* cov;        // 6 x n_pad SoA covariances
     const float* nrm;        // 3 x n_pad SoA normals or nullptr
     const double* anchor;    // n_chunks x 3 absolute anchors (source frame)
-    const float* crad;       // n_chunks: bound of the chunk's point offsets from its anchor (m)
+    const float* cbound;     // n_chunks x 8: chunk bounds around the anchor (m): box centre offset (3),
+                             //   ball radius, box half extents (3), 0
     const float* axyz;       // 3 x n_pad absolute FP32 positions
     const double* xyz64;     // 3 x n_pad absolute FP64 positions
     const double* cov64;     // 6 x n_pad FP64 covariances
@@ -134,7 +135,7 @@ struct vg_source {
     float* cov = nullptr;
     float* nrm = nullptr;
     double* anchor = nullptr;
-    float* crad = nullptr;     // per chunk: bound of |offset from the anchor| (m)
+    float* cbound = nullptr;   // per chunk: box centre offset (3), ball radius, box half extents (3), 0 (m)
     float* axyz = nullptr;
     double* xyz64 = nullptr;
     double* cov64 = nullptr;

@@ -430,23 +430,39 @@ __global__ void k_anchors(const double* __restrict__ xyz, const int32_t* __restr
     anchor[3 * c + 2] = s[2] * inv;
 }
 
-// Per chunk: an upper bound of the distance of its points from the anchor,
-// taken from the FP32 offsets the kernels read (FP64 squares, rounded up).
-__global__ void k_chunk_radius(const float* __restrict__ dxyz, int64_t n, int64_t n_pad, int64_t n_chunks,
-                               float* __restrict__ crad) {
+// FP32 value >= x (round up).
+__device__ __forceinline__ float f32_up(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = nextafterf(f, INFINITY);
+    return f;
+}
+
+// Per chunk, from the FP32 offsets the kernels read: a ball around the anchor
+// (radius bounds every point's distance) and an axis-aligned box in the source
+// frame (centre offset from the anchor, half extents bounding every point).
+__global__ void k_chunk_bounds(const float* __restrict__ dxyz, int64_t n, int64_t n_pad, int64_t n_chunks,
+                               float* __restrict__ cb) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_chunks) return;
     const int64_t i0 = c * kChunk;
     const int64_t i1 = (i0 + kChunk < n) ? i0 + kChunk : n;
-    double m = 0.0;
+    double m = 0.0, lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
     for (int64_t i = i0; i < i1; ++i) {
-        const double x = dxyz[i], y = dxyz[n_pad + i], z = dxyz[2 * n_pad + i];
-        m = fmax(m, x * x + y * y + z * z);
+        const double x[3] = {dxyz[i], dxyz[n_pad + i], dxyz[2 * n_pad + i]};
+        m = fmax(m, x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = (i == i0) ? x[a] : fmin(lo[a], x[a]);
+            hi[a] = (i == i0) ? x[a] : fmax(hi[a], x[a]);
+        }
     }
-    const double r = sqrt(m);
-    float rf = (float)r;
-    if ((double)rf < r) rf = nextafterf(rf, INFINITY);
-    crad[c] = rf;
+    float* o = cb + 8 * c;
+    for (int a = 0; a < 3; ++a) {
+        const float ctr = (float)(0.5 * (lo[a] + hi[a]));
+        o[a] = ctr;
+        o[4 + a] = f32_up(fmax(hi[a] - (double)ctr, (double)ctr - lo[a]));
+    }
+    o[3] = f32_up(sqrt(m));
+    o[7] = 0.f;
 }
 
 vg_status layout_source(vg_context* ctx, vg_source* s, const double* d_xyz, const double* d_cov,
@@ -479,7 +495,7 @@ vg_status layout_source(vg_context* ctx, vg_source* s, const double* d_xyz, cons
         k_layout<<<grid_of(n_pad), 256, 0, st>>>(d_xyz, d_cov, d_nrm, idx2, n, n_pad, s->dxyz, s->cov, s->nrm,
                                                  s->anchor, s->axyz, s->xyz64, s->cov64, s->nrm64, s->perm);
         if ((e = hipGetLastError()) != hipSuccess) break;
-        k_chunk_radius<<<grid_of(s->n_chunks), 256, 0, st>>>(s->dxyz, n, n_pad, s->n_chunks, s->crad);
+        k_chunk_bounds<<<grid_of(s->n_chunks), 256, 0, st>>>(s->dxyz, n, n_pad, s->n_chunks, s->cbound);
         if ((e = hipGetLastError()) != hipSuccess) break;
         e = hipStreamSynchronize(st);
     } while (0);
@@ -519,7 +535,7 @@ vg_status set_source_points(vg_context* ctx, vg_source* s, const void* d_xyz, in
                                                                      s->n_pad, s->dxyz, s->axyz, s->xyz64);
     VG_HIP(hipGetLastError());
     // the offsets moved: so do the chunk bounds
-    k_chunk_radius<<<grid_of(s->n_chunks), 256, 0, ctx->stream>>>(s->dxyz, s->n, s->n_pad, s->n_chunks, s->crad);
+    k_chunk_bounds<<<grid_of(s->n_chunks), 256, 0, ctx->stream>>>(s->dxyz, s->n, s->n_pad, s->n_chunks, s->cbound);
     VG_HIP(hipGetLastError());
     return VG_OK;
 }

@@ -257,11 +257,13 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
 #pragma unroll
     for (int k = 0; k < 6; ++k) W[k] = (float)W64[k];
     const float mv[3] = {q0.x, q0.y, q0.z};
+    // y - voxel centre in FP64: (anchor remainder - r/2) + R offset - jk r (jk r exact)
     const double ddx = dx, ddy = dy, ddz = dz;
+    const double half = 0.5 * lv.r64;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double y64 = sh.frac[3 * c + a] + (P[3 * a] * ddx + P[3 * a + 1] * ddy + P[3 * a + 2] * ddz);
-        d[a] = (float)((double)mv[a] - (y64 - ((double)jk[a] + 0.5) * lv.r64));
+        const double t = fma(P[3 * a + 2], ddz, fma(P[3 * a + 1], ddy, fma(P[3 * a], ddx, sh.frac[3 * c + a] - half)));
+        d[a] = (float)((double)mv[a] - fma(-(double)jk[a], lv.r64, t));
     }
     add_lin_terms(acc, d, W, z);
 }
@@ -698,10 +700,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 if constexpr (PREC == kC32) {
                     // y relative to the centre of the voxel found above (FP64), then d = mu~ - y
                     const double ddx = cur.x[0], ddy = cur.x[1], ddz = cur.x[2];
+                    const double half = 0.5 * lv.r64;
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        const double y64 = sh.frac[3 * c + a] + (P[3 * a] * ddx + P[3 * a + 1] * ddy + P[3 * a + 2] * ddz);
-                        d[a] = (float)((double)mv[a] - (y64 - ((double)jk[a] + 0.5) * lv.r64));
+                        const double t = fma(P[3 * a + 2], ddz,
+                                             fma(P[3 * a + 1], ddy, fma(P[3 * a], ddx, sh.frac[3 * c + a] - half)));
+                        d[a] = (float)((double)mv[a] - fma(-(double)jk[a], lv.r64, t));
                     }
                 } else {
 #pragma unroll

@@ -138,14 +138,16 @@ vg_status vg_voxelmap_destroy(vg_voxelmap* map);
 
 /* Upload a source Gaussian cloud (host FP64: xyz n x 3, cov n x 6, normals n x 3
  * or NULL).  The library reorders points internally along a Morton curve and
- * stores them relative to per-64-point anchors; every per-point output of the
- * library is reported in the caller's order.  Covariances must be SPD
- * (VG_ERR_NOT_SPD otherwise). */
+ * stores them relative to per-64-point anchors, with a ball and a box that
+ * bound each 64-point chunk (chunks that cannot reach a target's voxels are
+ * skipped by the kernels); every per-point output of the library is reported
+ * in the caller's order.  Covariances must be SPD (VG_ERR_NOT_SPD otherwise). */
 vg_status vg_create_source(vg_context* ctx, const double* xyz, const double* cov, const double* normals,
                            int64_t n, vg_source** out);
 /* Replace the source positions from a device buffer in caller order (n x 3,
  * dtype 0 = float32, 1 = float64), stream-ordered; covariances and normals are
- * kept.  Used to differentiate with respect to the points. */
+ * kept, the anchors too (offsets are taken from the old anchors), and the chunk
+ * bounds are recomputed.  Used to differentiate with respect to the points. */
 vg_status vg_source_set_points_async(vg_source* src, const void* d_xyz, int32_t dtype);
 vg_status vg_source_destroy(vg_source* src);
 

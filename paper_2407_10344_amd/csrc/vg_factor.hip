@@ -273,6 +273,39 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
 template <int PREC, bool KH>
 constexpr int waves_per_eu() { return (PREC == kF64 || KH) ? 1 : 4; }
 
+// Every point of chunk cg lies in a ball around the anchor and in a box of
+// the source frame, both stored with the chunk.  In the target frame (anchor
+// at ya) the ball keeps its radius and the box is covered by the axis-aligned
+// box of half extents |R| h.  A chunk whose ball or box misses the key box of
+// every level has no correspondence.  The margins (1e-3 m + 1e-5 relative)
+// cover FP32 key positions and the FP32 rounding of the stored offsets.
+__device__ __forceinline__ bool chunk_reaches(const FactorDesc* __restrict__ Fp, const double* P, const double ya[3],
+                                              int64_t cg, int L) {
+    const auto cb = gbl(Fp->cbound + 8 * cg);
+    const double rr = (double)cb[3] * (1.0 + 1e-5) + 1e-3;
+    double yc[3], ex[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        yc[i] = ya[i] + (P[3 * i] * cb[0] + P[3 * i + 1] * cb[1] + P[3 * i + 2] * cb[2]);
+        ex[i] = (fabs(P[3 * i]) * cb[4] + fabs(P[3 * i + 1]) * cb[5] + fabs(P[3 * i + 2]) * cb[6]) * (1.0 + 1e-5) +
+                1e-3;
+    }
+    bool reach = false;
+    for (int l = 0; l < L; ++l) {
+        const LevelDesc& lv = Fp->lv[l];
+        double d2 = 0.0;
+        bool box = true;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double g = fmax(0.0, fmax(lv.blo[i] - ya[i], ya[i] - lv.bhi[i]));
+            d2 += g * g;
+            box = box && (yc[i] + ex[i] >= lv.blo[i]) && (yc[i] - ex[i] <= lv.bhi[i]);
+        }
+        reach |= (d2 <= rr * rr) && box;
+    }
+    return reach;
+}
+
 // Pose staging: FP32 copies of every factor's R and t (16 floats per factor),
 // read by the tile kernel through uniform (scalar) loads.
 __global__ void k_stage_poses(int64_t F, const double* __restrict__ poses, float* __restrict__ posef) {
@@ -294,8 +327,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
     constexpr int NT = (MODE == kLin) ? kTerms : (MODE == kBwd ? 6 : 1);
     constexpr bool CMP = (MODE == kLin && PREC == kC32);   // compacted hits
     // chunks that cannot reach any level's key box are skipped (not in the
-    // backward pass, which writes a gradient row for every point)
-    constexpr bool SKIP = (PREC == kC32 && MODE != kBwd);
+    // backward pass, which writes a gradient row for every point, nor in the
+    // naive FP32 mode, whose absolute-coordinate keys can be off by more than
+    // the culling margin far from the origin)
+    constexpr bool SKIP = ((PREC == kC32 || PREC == kF64) && MODE != kBwd);
     __shared__ TileShared sh;
     using QueueT = typename std::conditional<CMP, HitQueue, int32_t>::type;
     __shared__ QueueT s_q[CMP ? NW : 1];
@@ -400,38 +435,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     sh.vc[3 * c + 1] = (float)(a1 - cs[1]);
                     sh.vc[3 * c + 2] = (float)(a2 - cs[2]);
                 }
-                if constexpr (SKIP) {
-                    // Every point of the chunk lies in a ball around the anchor and in
-                    // a box of the source frame, both stored with the chunk.  In the
-                    // target frame the ball keeps its radius and the box is covered
-                    // by the axis-aligned box of half extents |R| h; a chunk whose
-                    // ball or box misses the key box of every level has no
-                    // correspondence and is not walked.  The margins (1e-3 m + 1e-5
-                    // relative) cover the FP32 key positions.
-                    const auto cb = gbl(Fp->cbound + 8 * (int64_t)(tile.chunk0 + c));
-                    const double rr = (double)cb[3] * (1.0 + 1e-5) + 1e-3;
-                    double yc[3], ex[3];
+                if constexpr (SKIP) sh.reach[c] = chunk_reaches(Fp, P, ya, tile.chunk0 + c, L) ? 1 : 0;
+            }
+            __syncthreads();
+        } else if constexpr (SKIP) {
+            for (int c = threadIdx.x; c < tile.nchunks; c += BLOCK) {
+                const auto a = gbl(Fp->anchor + 3 * (int64_t)(tile.chunk0 + c));
+                double ya[3];
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        yc[i] = ya[i] + (P[3 * i] * cb[0] + P[3 * i + 1] * cb[1] + P[3 * i + 2] * cb[2]);
-                        ex[i] = (fabs(P[3 * i]) * cb[4] + fabs(P[3 * i + 1]) * cb[5] + fabs(P[3 * i + 2]) * cb[6]) *
-                                    (1.0 + 1e-5) + 1e-3;
-                    }
-                    bool reach = false;
-                    for (int l = 0; l < L; ++l) {
-                        const LevelDesc& lv = Fp->lv[l];
-                        double d2 = 0.0;
-                        bool box = true;
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) {
-                            const double g = fmax(0.0, fmax(lv.blo[i] - ya[i], ya[i] - lv.bhi[i]));
-                            d2 += g * g;
-                            box = box && (yc[i] + ex[i] >= lv.blo[i]) && (yc[i] - ex[i] <= lv.bhi[i]);
-                        }
-                        reach |= (d2 <= rr * rr) && box;
-                    }
-                    sh.reach[c] = reach ? 1 : 0;
-                }
+                for (int i = 0; i < 3; ++i) ya[i] = fma(P[3 * i + 2], a[2], fma(P[3 * i + 1], a[1], P[3 * i] * a[0])) + P[9 + i];
+                sh.reach[c] = chunk_reaches(Fp, P, ya, tile.chunk0 + c, L) ? 1 : 0;
             }
             __syncthreads();
         }

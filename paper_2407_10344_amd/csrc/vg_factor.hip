@@ -268,6 +268,43 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
     add_lin_terms(acc, d, W, z);
 }
 
+// Terms of one queued hit in the FP64 mode: the point is re-read from the
+// FP64 positions (it was read one drain ago, so the load hits the caches) and
+// the arithmetic is the uncompacted FP64 path's.
+template <typename A>
+__device__ __forceinline__ void cmp_hit_terms64(A& acc, const FactorDesc* __restrict__ Fp, const double* P,
+                                                const double* R, const double* tt, int64_t n_pad, int32_t i,
+                                                int32_t v, int32_t cl) {
+    const LevelDesc& lv = Fp->lv[cl & 3];
+    const auto X = gbl(Fp->xyz64);
+    const double x[3] = {X[i], X[n_pad + i], X[2 * n_pad + i]};
+    const auto r2 = gbl(reinterpret_cast<const f64x2*>(lv.rec64 + (int64_t)v * kRec64));
+    const f64x2 q0 = r2[0], q1 = r2[1], q2 = r2[2], q3 = r2[3], q4 = r2[4];
+    double S[6];
+    point_S<kF64>(Fp, (int64_t)i, n_pad, P, R, S);
+    double z[3], d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) z[a] = R[3 * a] * x[0] + R[3 * a + 1] * x[1] + R[3 * a + 2] * x[2];
+    d[0] = q0.x - (z[0] + tt[0]);
+    d[1] = q0.y - (z[1] + tt[1]);
+    d[2] = q1.x - (z[2] + tt[2]);
+    const double M[6] = {q1.y + S[0], q2.x + S[1], q2.y + S[2], q3.x + S[3], q3.y + S[4], q4.x + S[5]};
+    double W[6];
+    sym3_inverse(M, W);
+    add_lin_terms(acc, d, W, z);
+}
+
+// One queued hit, by precision mode.
+template <int PREC, typename A, typename T>
+__device__ __forceinline__ void drain_hit(A& acc, const FactorDesc* __restrict__ Fp, const TileShared& sh,
+                                          const double* P, const T* R, const T* tt, int64_t n_pad,
+                                          const HitQueue& Q, int e) {
+    if constexpr (PREC == kC32)
+        cmp_hit_terms(acc, Fp, sh, P, R, n_pad, Q.x[e], Q.y[e], Q.z[e], Q.pt[e], Q.rec[e], Q.cl[e]);
+    else
+        cmp_hit_terms64(acc, Fp, P, R, tt, n_pad, Q.pt[e], Q.rec[e], Q.cl[e]);
+}
+
 // Register budget: 4 waves per SIMD (<= 128 VGPRs) for the FP32 modes; the
 // FP64 mode needs more and runs at what its register count allows.
 template <int PREC, bool KH>
@@ -325,7 +362,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
     constexpr int NW = BLOCK / 64;
     constexpr bool KAHAN = KH && (PREC == kC32);
     constexpr int NT = (MODE == kLin) ? kTerms : (MODE == kBwd ? 6 : 1);
-    constexpr bool CMP = (MODE == kLin && PREC == kC32);   // compacted hits
+    constexpr bool CMP = (MODE == kLin && (PREC == kC32 || PREC == kF64));   // compacted hits
     // chunks that cannot reach any level's key box are skipped (not in the
     // backward pass, which writes a gradient row for every point, nor in the
     // naive FP32 mode, whose absolute-coordinate keys can be off by more than
@@ -493,7 +530,56 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 const int64_t in = (int64_t)(tile.chunk0 + cn) * kChunk + lane;
                 if (in < n) load_point<PREC>(Fp, in, n_pad, nxt);
             }
-            if constexpr (CMP) {
+            if constexpr (CMP && PREC == kF64) {
+                // ---- FP64 mode: probe every point, queue its hits, drain full waves
+                HitQueue& Q = s_q[wave];
+                const bool live = i < n;
+                const double x0 = cur.x[0], x1 = cur.x[1], x2 = cur.x[2];
+                double yl[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) yl[a] = (R[3 * a] * x0 + R[3 * a + 1] * x1 + R[3 * a + 2] * x2) + tt[a];
+                bool vis = live;
+                if (live && validate) {
+                    const auto Nv = gbl(Fp->nrm64);
+                    const double sv = (x0 - cs[0]) * Nv[i] + (x1 - cs[1]) * Nv[n_pad + i] + (x2 - cs[2]) * Nv[2 * n_pad + i];
+                    vis = !(sv > 0.0);
+                }
+#pragma unroll
+                for (int l = 0; l < kMaxLevels; ++l) {
+                    if (l >= L) break;
+                    const LevelDesc& lv = Fp->lv[l];
+                    int32_t kq[3];
+                    bool in = vis;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const int64_t k = (int64_t)floor(yl[a] * lv.inv_r64) - lv.K0[a];
+                        in &= (k >= lv.kmin[a]) & (k <= lv.kmax[a]);
+                        kq[a] = (int32_t)k;
+                    }
+                    int32_t v = -1;
+                    if (in) v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
+                    const bool hit = v >= 0;
+                    inl[l] += hit ? 1 : 0;
+                    const uint64_t mask = __ballot(hit);
+                    const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                    if (hit) {
+                        const int e = (q_head + q_count + below) & (kQueue - 1);
+                        Q.pt[e] = (int32_t)i;
+                        Q.rec[e] = v;
+                        Q.cl[e] = (c << 2) | l;
+                    }
+                    q_count += __popcll(mask);
+                    if (q_count >= kChunk) {
+                        __builtin_amdgcn_wave_barrier();
+                        drain_hit<PREC>(acc, Fp, sh, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
+                        q_head = (q_head + kChunk) & (kQueue - 1);
+                        q_count -= kChunk;
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+                continue;
+            } else if constexpr (CMP) {
                 // ---- probe every point, queue its hits, drain full waves of hits
                 HitQueue& Q = s_q[wave];
                 const bool live = i < n;
@@ -542,8 +628,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     q_count += __popcll(mask);
                     if (q_count >= kChunk) {
                         __builtin_amdgcn_wave_barrier();
-                        const int e = (q_head + lane) & (kQueue - 1);
-                        cmp_hit_terms(acc, Fp, sh, P, R, n_pad, Q.x[e], Q.y[e], Q.z[e], Q.pt[e], Q.rec[e], Q.cl[e]);
+                        drain_hit<PREC>(acc, Fp, sh, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
                         q_head = (q_head + kChunk) & (kQueue - 1);
                         q_count -= kChunk;
                         __builtin_amdgcn_wave_barrier();
@@ -782,9 +867,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
             if (q_count > 0) {
                 __builtin_amdgcn_wave_barrier();
                 if (lane < q_count) {
-                    HitQueue& Q = s_q[wave];
-                    const int e = (q_head + lane) & (kQueue - 1);
-                    cmp_hit_terms(acc, Fp, sh, P, R, n_pad, Q.x[e], Q.y[e], Q.z[e], Q.pt[e], Q.rec[e], Q.cl[e]);
+                    drain_hit<PREC>(acc, Fp, sh, P, R, tt, n_pad, s_q[wave], (q_head + lane) & (kQueue - 1));
                 }
                 __builtin_amdgcn_wave_barrier();
             }

@@ -1179,12 +1179,15 @@ extern "C" vg_status vg_batch_tune(vg_batch* b, const double* poses, int32_t rep
     // candidates in order of preference: a later candidate replaces an earlier one
     // only when it is faster by more than 1.5 %, so timing noise does not flip the choice
     const int orders[] = {1, 2};
-    const int tiles[] = {8192, 4096, 2048, 1024};
+    const int tiles[] = {8192, 4096, 2048, 1024, 512, 256};
     const int blocks[] = {256, 128, 512};
     const int occ[] = {2, 1, 4};   // multiples of the full-occupancy workgroup count
     float best = 1e30f;
     int bb = b->block, bt = b->tile_points, bc = b->blocks_per_cu, bo = b->tile_order;
     for (int tp : tiles) {
+        // the small tiles are for small batches (more tiles than workgroups);
+        // a batch that fills the device with 1024-point tiles skips them
+        if (tp < 1024 && b->total_points / tp > (int64_t)(1 << 20)) continue;
         b->tile_points = tp;
         build_tiles(b);
         VG_TRY(upload_schedule(b));

@@ -264,7 +264,7 @@ def summarize_profiles(kt_dir, fetch_dir, write_dir, command, tile_points, tile_
     lines = [
         "# rocprofv3 summary: tile kernel k_tiles<lin, fp32c> (linearize, compensated FP32), %s" % workload,
         "#",
-        "# commands (from /tmp, TMPDIR=/tmp, repository root as %s):" % "$GRAFT_REPO_ROOT",
+        "# commands (from /tmp, TMPDIR=/tmp, REPO = the repository root):",
     ] + ["#   " + c for c in command] + [
         "#",
         "kernel: %s" % tile["Name"].split("(")[0],

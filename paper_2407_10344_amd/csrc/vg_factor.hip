@@ -158,10 +158,11 @@ struct TileShared {
 // expensive part (record gather, fused covariance and its inverse, residual,
 // 28 terms) only on full waves of hits.  Ring of 128 entries: a push adds at
 // most 64 (one level of one chunk) and a full wave of 64 is drained as soon as
-// 64 are queued, so at most 127 are ever held.
+// 64 are queued, so at most 127 are ever held.  The FP64 mode leaves x, y, z
+// unused (its drain re-reads the FP64 position).
 constexpr int kQueue = 128;
 struct HitQueue {
-    float x[kQueue], y[kQueue], z[kQueue];   // point offset from its chunk anchor
+    float x[kQueue], y[kQueue], z[kQueue];   // point offset from its chunk anchor (compensated mode)
     int32_t pt[kQueue];                      // point index in the source (internal order)
     int32_t rec[kQueue];                     // voxel record index
     int32_t cl[kQueue];                      // chunk in tile (bits 2..) and level (bits 0..1)
@@ -505,7 +506,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
         // ---------------------------------------------------------------- per-point work
         Acc<T, KAHAN, NT> acc;
         acc.zero();
-        int32_t inl[kMaxLevels] = {0, 0, 0, 0};
+        int32_t inl[kMaxLevels] = {0, 0, 0, 0};   // per lane (wave totals in the compacted paths)
         double ge = 0.0;
         if constexpr (MODE == kBwd) ge = grad_e[tile.factor];
 
@@ -559,8 +560,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     int32_t v = -1;
                     if (in) v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
                     const bool hit = v >= 0;
-                    inl[l] += hit ? 1 : 0;
                     const uint64_t mask = __ballot(hit);
+                    inl[l] += __popcll(mask);   // wave-uniform count
                     const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
                     if (hit) {
@@ -612,8 +613,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     }
                     if (in) v = lookup(pl.slots, pl.log2cap, kq[0], kq[1], kq[2]);
                     const bool hit = v >= 0;
-                    inl[l] += hit ? 1 : 0;
                     const uint64_t mask = __ballot(hit);
+                    inl[l] += __popcll(mask);   // wave-uniform count
                     const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
                     if (hit) {
@@ -887,7 +888,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
         if constexpr (MODE != kBwd) {
 #pragma unroll
             for (int l = 0; l < kMaxLevels; ++l) {
-                const int32_t v = wave_sum(inl[l]);
+                const int32_t v = CMP ? inl[l] : wave_sum(inl[l]);
                 if (lane == 0) s_red[wave][kTerms + l] = (double)v;
             }
         }

@@ -135,9 +135,12 @@ struct ProbeLevel {
     float inv_r;
     int32_t kbox0[3];
     uint32_t kboxw[3];
+    const float* rec32;   // read by the hit terms of the first level
+    double r64;
     __device__ __forceinline__ explicit ProbeLevel(const LevelDesc& lv)
         : slots(lv.slots), log2cap(lv.log2cap), log2scale((uint32_t)lv.log2scale), inv_r(lv.inv_r),
-          kbox0{lv.kbox0[0], lv.kbox0[1], lv.kbox0[2]}, kboxw{lv.kboxw[0], lv.kboxw[1], lv.kboxw[2]} {}
+          kbox0{lv.kbox0[0], lv.kbox0[1], lv.kbox0[2]}, kboxw{lv.kboxw[0], lv.kboxw[1], lv.kboxw[2]},
+          rec32(lv.rec32), r64(lv.r64) {}
 };
 
 // Per-tile chunk data in LDS.  At 4 waves per SIMD a CU holds at most 16
@@ -228,11 +231,21 @@ __device__ __forceinline__ void point_S(const FactorDesc* __restrict__ Fp, int64
 // uncompacted path, with the point's chunk and level taken from the entry.
 template <typename A>
 __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restrict__ Fp, const TileShared& sh,
-                                              const double* P, const float* R, int64_t n_pad, float dx, float dy,
-                                              float dz, int32_t i, int32_t v, int32_t cl) {
+                                              const ProbeLevel& pl0, const double* P, const float* R, int64_t n_pad,
+                                              float dx, float dy, float dz, int32_t i, int32_t v, int32_t cl) {
     const int c = cl >> 2, l = cl & 3;
-    const LevelDesc& lv = Fp->lv[l];
-    const float* rec = lv.rec32 + (int64_t)v * kRec32;
+    // the level's record array, 1/r and r: the first level's come from scalar
+    // registers, so its record gather does not wait on a descriptor load
+    const float* rec_base = pl0.rec32;
+    float inv_r = pl0.inv_r;
+    double r64 = pl0.r64;
+    if (l != 0) {
+        const LevelDesc& lv = Fp->lv[l];
+        rec_base = lv.rec32;
+        inv_r = lv.inv_r;
+        r64 = lv.r64;
+    }
+    const float* rec = rec_base + (int64_t)v * kRec32;
     const f32x4 q0 = *gbl(reinterpret_cast<const f32x4*>(rec));
     const auto c2 = gbl(reinterpret_cast<const f64x2*>(rec + 4));
     const f64x2 cva = c2[0], cvb = c2[1], cvc = c2[2];
@@ -243,7 +256,7 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float yl = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
-        jk[a] = floor_i32(yl * lv.inv_r);
+        jk[a] = floor_i32(yl * inv_r);
         z[a] = sh.za[3 * c + a] + fmaf(R[3 * a + 2], dz, fmaf(R[3 * a + 1], dy, R[3 * a] * dx));
     }
     double M[6], W64[6];
@@ -260,11 +273,11 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
     const float mv[3] = {q0.x, q0.y, q0.z};
     // y - voxel centre in FP64: (anchor remainder - r/2) + R offset - jk r (jk r exact)
     const double ddx = dx, ddy = dy, ddz = dz;
-    const double half = 0.5 * lv.r64;
+    const double half = 0.5 * r64;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double t = fma(P[3 * a + 2], ddz, fma(P[3 * a + 1], ddy, fma(P[3 * a], ddx, sh.frac[3 * c + a] - half)));
-        d[a] = (float)((double)mv[a] - fma(-(double)jk[a], lv.r64, t));
+        d[a] = (float)((double)mv[a] - fma(-(double)jk[a], r64, t));
     }
     add_lin_terms(acc, d, W, z);
 }
@@ -298,10 +311,10 @@ __device__ __forceinline__ void cmp_hit_terms64(A& acc, const FactorDesc* __rest
 // One queued hit, by precision mode.
 template <int PREC, typename A, typename T>
 __device__ __forceinline__ void drain_hit(A& acc, const FactorDesc* __restrict__ Fp, const TileShared& sh,
-                                          const double* P, const T* R, const T* tt, int64_t n_pad,
-                                          const HitQueue& Q, int e) {
+                                          const ProbeLevel& pl0, const double* P, const T* R, const T* tt,
+                                          int64_t n_pad, const HitQueue& Q, int e) {
     if constexpr (PREC == kC32)
-        cmp_hit_terms(acc, Fp, sh, P, R, n_pad, Q.x[e], Q.y[e], Q.z[e], Q.pt[e], Q.rec[e], Q.cl[e]);
+        cmp_hit_terms(acc, Fp, sh, pl0, P, R, n_pad, Q.x[e], Q.y[e], Q.z[e], Q.pt[e], Q.rec[e], Q.cl[e]);
     else
         cmp_hit_terms64(acc, Fp, P, R, tt, n_pad, Q.pt[e], Q.rec[e], Q.cl[e]);
 }
@@ -573,7 +586,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     q_count += __popcll(mask);
                     if (q_count >= kChunk) {
                         __builtin_amdgcn_wave_barrier();
-                        drain_hit<PREC>(acc, Fp, sh, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
+                        drain_hit<PREC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
                         q_head = (q_head + kChunk) & (kQueue - 1);
                         q_count -= kChunk;
                         __builtin_amdgcn_wave_barrier();
@@ -629,7 +642,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     q_count += __popcll(mask);
                     if (q_count >= kChunk) {
                         __builtin_amdgcn_wave_barrier();
-                        drain_hit<PREC>(acc, Fp, sh, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
+                        drain_hit<PREC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
                         q_head = (q_head + kChunk) & (kQueue - 1);
                         q_count -= kChunk;
                         __builtin_amdgcn_wave_barrier();
@@ -868,7 +881,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
             if (q_count > 0) {
                 __builtin_amdgcn_wave_barrier();
                 if (lane < q_count) {
-                    drain_hit<PREC>(acc, Fp, sh, P, R, tt, n_pad, s_q[wave], (q_head + lane) & (kQueue - 1));
+                    drain_hit<PREC>(acc, Fp, sh, pl0, P, R, tt, n_pad, s_q[wave], (q_head + lane) & (kQueue - 1));
                 }
                 __builtin_amdgcn_wave_barrier();
             }

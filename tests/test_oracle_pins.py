@@ -416,3 +416,79 @@ def test_visibility_rule():
     tr = f.linearize(T, trace=True)
     cs = T[:3, :3].T @ (view - T[:3, 3])
     assert tr["visible"][0] == (not ((mu[0] - cs) @ up[0] > 0))
+
+
+def _lm_case():
+    cfg = synth.config1(seed=44, n_target=6000, n_source=1500, angle_deg=2.0, trans_m=0.2)
+    f = oracle.factor_from_clouds(cfg["sources"][0], cfg["targets"][0], cfg["resolutions"])
+    return f, np.asarray(cfg["poses"][0], dtype=np.float64)
+
+
+@pytest.mark.parametrize("lam", [1e-4, 1.0, 30.0])
+def test_lm_step_is_marquardt_damped_gauss_newton(lam):
+    """One LM iteration proposes T Exp(delta) with delta = solve(H + lambda diag(H), -b) on the
+    oracle's H and b (numpy solve, scipy expm); it is kept iff the error drops, and lambda is
+    then divided by 10, else multiplied by 10.  At lambda = 30 the Marquardt step differs from
+    the lambda*I step by far more than the tolerance, so the damping form is pinned."""
+    f, T = _lm_case()
+    r = f.linearize(T)
+    H, b = r["H"], r["b"]
+    delta = np.linalg.solve(H + lam * np.diag(np.diag(H)), -b)
+    delta_eye = np.linalg.solve(H + lam * np.eye(6), -b)
+    Tn = retract(T, delta)
+    better = f.evaluate(Tn) < r["e"]
+    out = f.lm(T, iters=1, lambda0=lam)
+    assert out["e"][0] == r["e"]
+    assert bool(out["accepted"][0]) == better
+    if better:
+        np.testing.assert_allclose(out["pose"], Tn, rtol=0, atol=1e-12)
+        assert out["lambda"] == lam / 10.0
+    else:
+        np.testing.assert_array_equal(out["pose"], T)
+        assert out["lambda"] == lam * 10.0
+    if lam >= 1.0:
+        assert np.linalg.norm(delta - delta_eye) > 1e3 * 1e-12 * np.linalg.norm(delta)
+        assert not np.allclose(retract(T, delta_eye), Tn, rtol=0, atol=1e-9)
+    assert better or lam > 1.0
+
+
+def test_lm_schedule_over_iterations():
+    """Ten iterations: the accept flags follow 'error drops', lambda follows /10 and x10, and
+    each recorded error is the error at the pose the iteration linearized at (the expected
+    poses are advanced with scipy's expm, so they agree with the oracle's to rounding)."""
+    f, T = _lm_case()
+    lam = 1e-4
+    out = f.lm(T, iters=10, lambda0=lam)
+    for it in range(10):
+        r = f.linearize(T)
+        assert abs(out["e"][it] - r["e"]) <= 1e-10 * r["e"], it   # poses differ by exp rounding
+        delta = np.linalg.solve(r["H"] + lam * np.diag(np.diag(r["H"])), -r["b"])
+        Tn = retract(T, delta)
+        acc = f.evaluate(Tn) < r["e"]
+        assert bool(out["accepted"][it]) == acc, it
+        if acc:
+            T = Tn
+            lam /= 10.0
+        else:
+            lam *= 10.0
+    assert out["lambda"] == lam
+    np.testing.assert_allclose(out["pose"], T, rtol=0, atol=1e-10)
+
+
+def test_lm_forced_rejects_multiply_lambda_by_ten():
+    """No correspondence (H = 0: the damped system is singular) and a zero-residual optimum
+    (delta = 0: the error cannot drop) both reject, keep the pose and multiply lambda by 10."""
+    f, T = _lm_case()
+    far = T.copy()
+    far[:3, 3] += [1e4, 0.0, 0.0]
+    out = f.lm(far, iters=3, lambda0=1e-4)
+    assert not out["accepted"].any() and out["e"].tolist() == [0.0] * 3
+    np.testing.assert_array_equal(out["pose"], far)
+    assert out["lambda"] == 1e-4 * 10 * 10 * 10
+    cloud, res = synth.tiny_lattice_pair(2, resolutions=(1.0,))
+    vm = oracle.VoxelMap(cloud.xyz64(), cloud.cov64(), res)
+    g = oracle.Factor(cloud.xyz64(), cloud.cov64(), vm)
+    out = g.lm(np.eye(4), iters=2, lambda0=1e-4)
+    assert out["e"].tolist() == [0.0, 0.0] and not out["accepted"].any()
+    np.testing.assert_array_equal(out["pose"], np.eye(4))
+    assert out["lambda"] == 1e-4 * 10 * 10

@@ -64,10 +64,20 @@ typedef enum {
     VG_ERR_STATE = -7        /* handle in use, destroyed, or from another context */
 } vg_status;
 
+/* Precision of a batch.  Re-centring is part of the compensated mode, not a
+ * separate switch: that mode stores every source point as an FP32 offset from
+ * an FP64 anchor of its 64-point chunk and every voxel mean relative to its
+ * voxel centre, so there are no absolute FP32 coordinates to re-centre, and
+ * VG_FP32 is the absolute-coordinate (not re-centred) form.  The compensated
+ * mode is value 0 so that zero-initialised options select it. */
 typedef enum {
     VG_FP32_COMPENSATED = 0, /* FP32 terms in re-centred coordinates; residual and fused
                                 covariance formed in FP64; FP64 sums across lanes, waves,
-                                tiles and factors (the default) */
+                                tiles and factors (the default).  Sources must lie within
+                                500 m of their origin (the first point rounded to a metre):
+                                the per-point lever arms are FP32, and beyond that the
+                                relative error of b can exceed 1e-5.  A batch with a larger
+                                source is refused (VG_ERR_INVALID_ARG); use VG_FP64. */
     VG_FP32 = 1,             /* absolute FP32 coordinates, FP32 accumulation end to end */
     VG_FP64 = 2              /* FP64 data and arithmetic throughout */
 } vg_precision;
@@ -126,7 +136,9 @@ vg_status vg_build_voxelmap(vg_context* ctx, const double* xyz, const double* co
  * voxels are grouped in 4x4x4 blocks, one hash entry per occupied block. */
 vg_status vg_voxelmap_info(const vg_voxelmap* map, int32_t level, int64_t* n_voxels,
                            int64_t* capacity);
-/* Copy a level to the host in canonical order (ascending lexicographic key).
+/* Copy a level to the host in canonical order (ascending lexicographic key):
+ * the per-voxel mean of the member points' means and mean of their
+ * covariances (Sec. III-C, Preprocessing), for parity checks.
  * Any output may be NULL.  keys: V x 3 absolute voxel coordinates; means: V x 3
  * and covs: V x 6 in FP64; counts: V.  `n_voxels` is in/out: capacity of the
  * outputs on entry, voxel count on return (VG_ERR_INVALID_ARG if too small). */
@@ -216,7 +228,9 @@ vg_status vg_batch_destroy(vg_batch* batch);
  * level) or NULL.  One upload and one download per call; synchronous. */
 vg_status vg_linearize(vg_batch* batch, const double* poses, double* e, double* H, double* b,
                        int64_t* inliers);
-/* Error only, with correspondences and W recomputed at the given poses. */
+/* Error only, e = sum d^T W d over points and levels (Eq. (em), Eq. (d2d)), with
+ * correspondences and W recomputed at the given poses (host arrays: poses
+ * F x 12 in, e F out; synchronous). */
 vg_status vg_evaluate(vg_batch* batch, const double* poses, double* e);
 
 /* Overlap rate of every factor at its pose (GLIM Sec. IV-B and V: the
@@ -232,13 +246,16 @@ vg_status vg_overlap(vg_batch* batch, const double* poses, double* overlap);
 vg_status vg_linearize_async(vg_batch* batch, const double* d_poses, double* d_out, int64_t* d_inliers);
 vg_status vg_evaluate_async(vg_batch* batch, const double* d_poses, double* d_e);
 
-/* Exact gradient of e (W recomputed, not frozen; correspondences held at the
- * given poses), scaled by d_grad_e (F).  d_jr: F x 36 FP64 right Jacobians
+/* Exact gradient of e (Eq. (em), Eq. (d2d); W recomputed, not frozen;
+ * correspondences held at the given poses), scaled by d_grad_e (F).  d_jr: F x 36 FP64 right Jacobians
  * J_r(xi) to apply (grad_xi = J_r^T de/dxi') or NULL for the plain tangent
  * gradient at T.  d_grad_xi: F x 6 FP64.  d_grad_points: per-point gradient of
  * every source of the batch in caller order, sources concatenated in order of
  * first use (n_total x 3; dtype 0 = float32, 1 = float64), or NULL.  A source
- * used by several factors receives the sum of their gradients. */
+ * used by several factors receives the sum of their gradients, formed in FP64
+ * in factor order (deterministic); the first such call on a batch allocates a
+ * per-factor gradient buffer (3 values per point of every factor whose source
+ * is shared) that the batch keeps. */
 vg_status vg_backward_async(vg_batch* batch, const double* d_poses, const double* d_grad_e,
                             const double* d_jr, double* d_grad_xi, void* d_grad_points,
                             int32_t points_dtype);
@@ -257,12 +274,31 @@ vg_status vg_se3_retract_async(vg_context* ctx, int64_t F, const double* d_T0, c
 vg_status vg_lm_run(vg_batch* batch, const double* poses_in, int32_t iters, double lambda0,
                     double* poses_out, int32_t* accepted, double* e_hist);
 
-/* Correspondences of one factor at a pose (host), for parity checks: keys
+/* Correspondences of one factor at a pose (Sec. III-C, Correspondence search:
+ * the voxel holding the transformed point at each level), for parity checks: keys
  * n x L x 3 absolute voxel coordinates of the transformed points, found n x L
  * (1 = voxel exists, 0 = none, -1 = point discarded by surface validation),
  * both in caller order.  Uses the batch's precision mode. */
 vg_status vg_correspondences(vg_batch* batch, const double* pose, int64_t factor, int64_t* keys,
                              int32_t* found);
+
+/* One Levenberg-Marquardt iteration for every factor (Sec. V-A), stream-ordered
+ * on device pointers with no host synchronization: linearize at d_poses (F x 12,
+ * in/out), solve (H + lambda diag(H)) delta = -b by FP64 Cholesky, evaluate
+ * T Exp(delta), and accept it iff e decreases (T <- T Exp(delta), lambda /= 10);
+ * otherwise T is kept and lambda *= 10 (a damped matrix that is not positive
+ * definite counts as a rejection).  d_lambda: F FP64, in/out.  d_e: F FP64, the
+ * error at the input poses, or NULL.  d_accepted: F int32 (1 = accepted), or
+ * NULL.  Uses the batch's result buffers, so calls on one batch must not overlap. */
+vg_status vg_lm_step_async(vg_batch* batch, double* d_poses, double* d_lambda, double* d_e, int32_t* d_accepted);
+
+/* Work done by the most recent linearize / evaluate / overlap call on the batch
+ * (synchronizes the context stream): per factor the source points and 64-point
+ * chunks walked (chunks whose bounds cannot reach any level's voxels are culled
+ * before their points are read), and the table lookups per level (F x L: point
+ * levels inside the level's key box; the rest are rejected without a memory
+ * access).  Any output may be NULL. */
+vg_status vg_batch_work(vg_batch* batch, int64_t* walked_points, int64_t* walked_chunks, int64_t* lookups);
 
 /* Autotune the launch shape of a batch at representative poses (host F x 12):
  * every candidate (block threads x tile points x workgroups per CU) is timed

@@ -61,6 +61,8 @@ def lib():
             L.orc_point_terms.argtypes = [P, P, C.c_int64, C.c_int32, P, P]
             L.orc_evaluate.restype = C.c_int
             L.orc_evaluate.argtypes = [P, P, P]
+            L.orc_gradient_scale.restype = C.c_int
+            L.orc_gradient_scale.argtypes = [P, P, P]
             L.orc_gradient.restype = C.c_int
             L.orc_gradient.argtypes = [P, P, P, P]
             L.orc_se3_exp.restype = None
@@ -192,6 +194,18 @@ class Factor:
         if st < 0:
             raise RuntimeError("orc_point_terms failed: %d" % st)
         return bool(st), out[0], out[1:37].reshape(6, 6), out[37:43]
+
+    def gradient_scale(self, pose):
+        """(sum over matched pairs of |b_k| of the rotation half, the same of the
+        translation half): the scale of b's summands, against which the error of a
+        sum that cancels is stated."""
+        pr, keep = self._problem()
+        T = as_pose12(pose)
+        out = np.zeros(2)
+        st = lib().orc_gradient_scale(C.byref(pr), _p(T), _p(out))
+        if st != 0:
+            raise RuntimeError("orc_gradient_scale failed: %d" % st)
+        return float(out[0]), float(out[1])
 
     def evaluate(self, pose, frozen=None, omega_pose=None):
         pr, keep = self._problem(frozen, omega_pose)

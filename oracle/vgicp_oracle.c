@@ -373,6 +373,41 @@ int orc_point_terms(const orc_problem *p, const double pose[12], int64_t k, int3
     return st == ORC_OK ? 1 : st;
 }
 
+/*
+ * Scale of the gradient's summands: over every matched (point, level) pair,
+ * the sum of the Euclidean norms of its contribution to the rotation half
+ * b[0..2] and to the translation half b[3..5] of b.  Near convergence the
+ * contributions cancel, so |b| is far below this sum; errors of a device sum
+ * are then stated against this scale.  out[0]: rotation half, out[1]:
+ * translation half.
+ */
+int orc_gradient_scale(const orc_problem *p, const double pose[12], double out[2]) {
+    out[0] = 0.0;
+    out[1] = 0.0;
+    const double *Rw = p->omega_pose ? p->omega_pose : pose;
+    for (int64_t k = 0; k < p->n; ++k) {
+        const double *mu = p->xyz + 3 * k;
+        int vis = p->frozen ? 1 : visible(p, pose, k);
+        double y[3];
+        transform(pose, mu, y);
+        for (int l = 0; l < p->L; ++l) {
+            const orc_level *lv = &p->levels[l];
+            int64_t q[3];
+            for (int a = 0; a < 3; ++a) q[a] = (int64_t)floor(y[a] / lv->r);
+            int64_t v;
+            if (p->frozen) v = p->frozen[k * p->L + l];
+            else v = vis ? orc_lookup(lv, q) : -1;
+            if (v < 0) continue;
+            double e1 = 0.0, H1[36] = {0}, b1[6] = {0};
+            int st = pair_terms(pose, Rw, mu, p->cov + 6 * k, lv->mean + 3 * v, lv->cov + 6 * v, &e1, H1, b1);
+            if (st != ORC_OK) return st;
+            out[0] += sqrt(b1[0] * b1[0] + b1[1] * b1[1] + b1[2] * b1[2]);
+            out[1] += sqrt(b1[3] * b1[3] + b1[4] * b1[4] + b1[5] * b1[5]);
+        }
+    }
+    return ORC_OK;
+}
+
 /* e at `pose` (correspondences and Omega recomputed there unless frozen). */
 int orc_evaluate(const orc_problem *p, const double pose[12], double *e) {
     double H[36], b[6];

@@ -88,6 +88,8 @@ SIGNATURES = {
     "vg_backward_async": (C.c_int, [P, P, P, P, P, P, I32]),
     "vg_se3_retract_async": (C.c_int, [P, I64, P, P, P, P]),
     "vg_lm_run": (C.c_int, [P, P, I32, D, P, P, P]),
+    "vg_lm_step_async": (C.c_int, [P, P, P, P, P]),
+    "vg_batch_work": (C.c_int, [P, P, P, P]),
     "vg_correspondences": (C.c_int, [P, P, I64, P, P]),
     "vg_batch_tune": (C.c_int, [P, P, I32, P]),
     "vg_create_graph": (C.c_int, [P, I64, I64, P, P, P]),

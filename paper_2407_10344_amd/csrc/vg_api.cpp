@@ -20,6 +20,13 @@ constexpr uint32_t kMapMagic = 0x3A900001u;
 constexpr uint32_t kSrcMagic = 0x50CE0001u;
 constexpr uint32_t kBatMagic = 0xBA7C0001u;
 
+// Largest distance (m) of a source point from its re-centring origin that the
+// compensated FP32 mode accepts: its per-point lever arms are FP32, and the
+// rotational part of b cancels across the cloud, so the relative error of b
+// grows with the extent (below 1e-6 for clouds of a few hundred metres, ~3e-4
+// for one spanning 4 km).
+constexpr double kMaxCompensatedExtent = 500.0;
+
 thread_local std::string g_err;
 
 bool finite_all(const double* p, int64_t n) {
@@ -319,6 +326,23 @@ static void free_source(vg_source* s) {
     dfree(s->perm);
 }
 
+// Upper bound of |mu - origin| over a source's points from its chunk anchors
+// and ball radii (host copy of both; synchronizes the context stream).
+static vg_status source_extent(vg_context* ctx, vg_source* s) {
+    std::vector<double> an(3 * s->n_chunks);
+    std::vector<float> cb(8 * s->n_chunks);
+    VG_HIP(hipMemcpyAsync(an.data(), s->anchor, sizeof(double) * an.size(), hipMemcpyDeviceToHost, ctx->stream));
+    VG_HIP(hipMemcpyAsync(cb.data(), s->cbound, sizeof(float) * cb.size(), hipMemcpyDeviceToHost, ctx->stream));
+    VG_HIP(hipStreamSynchronize(ctx->stream));
+    double ext = 0.0;
+    for (int64_t c = 0; c < s->n_chunks; ++c) {
+        const double dx = an[3 * c] - s->origin[0], dy = an[3 * c + 1] - s->origin[1], dz = an[3 * c + 2] - s->origin[2];
+        ext = std::max(ext, std::sqrt(dx * dx + dy * dy + dz * dz) + (double)cb[8 * c + 3]);
+    }
+    s->extent = ext;
+    return VG_OK;
+}
+
 // Source from device FP64 arrays (caller order); first = host copy of point 0.
 static vg_status make_source(vg_context* ctx, const double* d_xyz, const double* d_cov, const double* d_nrm,
                              bool has_normals, int64_t n, const double* first, vg_source** out) {
@@ -345,7 +369,8 @@ static vg_status make_source(vg_context* ctx, const double* d_xyz, const double*
             if ((st = dev_alloc(&s->nrm64, 3 * np)) != VG_OK) break;
         }
         if (n == 0) break;
-        st = layout_source(ctx, s, d_xyz, d_cov, d_nrm);
+        if ((st = layout_source(ctx, s, d_xyz, d_cov, d_nrm)) != VG_OK) break;
+        st = source_extent(ctx, s);
     } while (0);
     if (st != VG_OK) {
         free_source(s);
@@ -677,16 +702,25 @@ bool valid_shape(int block, int tile, int bpc) {
            tile / kChunk <= kMaxTileChunks && bpc >= 1 && bpc <= 64;
 }
 
-vg_status run_linearize_device(vg_batch* b, const double* d_poses, double* d_out, int64_t* d_inl) {
+// The batch's own buffers for the tile kernel and reduction.
+Workspace batch_ws(vg_batch* b) { return Workspace{b->d_partials, b->d_counter, b->d_posef, b->d_work}; }
+
+vg_status run_linearize_device(vg_batch* b, const Workspace& ws, const double* d_poses, double* d_out,
+                               int64_t* d_inl) {
     const int32_t nt = (int32_t)b->h_tiles.size();
-    VG_TRY(launch_tiles(b, kLin, d_poses, 0, nt, b->grid, nullptr, nullptr, 0, 0, b->F));
-    return launch_reduce(b, kLin, d_poses, 0, (int32_t)b->F, d_out, d_inl, nullptr, nullptr, nullptr);
+    VG_TRY(launch_tiles(b, ws, kLin, d_poses, 0, nt, b->grid, nullptr, nullptr, 0, 0, b->F));
+    return launch_reduce(b, ws, kLin, d_poses, 0, (int32_t)b->F, d_out, d_inl, nullptr, nullptr, nullptr);
+}
+
+vg_status run_linearize_device(vg_batch* b, const double* d_poses, double* d_out, int64_t* d_inl) {
+    return run_linearize_device(b, batch_ws(b), d_poses, d_out, d_inl);
 }
 
 vg_status run_evaluate_device(vg_batch* b, const double* d_poses, double* d_e) {
     const int32_t nt = (int32_t)b->h_tiles.size();
-    VG_TRY(launch_tiles(b, kEval, d_poses, 0, nt, b->grid, nullptr, nullptr, 0, 0, b->F));
-    return launch_reduce(b, kEval, d_poses, 0, (int32_t)b->F, d_e, nullptr, nullptr, nullptr, nullptr);
+    const Workspace ws = batch_ws(b);
+    VG_TRY(launch_tiles(b, ws, kEval, d_poses, 0, nt, b->grid, nullptr, nullptr, 0, 0, b->F));
+    return launch_reduce(b, ws, kEval, d_poses, 0, (int32_t)b->F, d_e, nullptr, nullptr, nullptr, nullptr);
 }
 
 // Capture [H2D poses, tile kernel, reduction, D2H results] once; replayed per call.
@@ -734,9 +768,10 @@ vg_status linearize_host(vg_batch* b) {
                                   hipMemcpyHostToDevice, st));
             const int32_t t0 = b->h_tile_first[f], t1 = b->h_tile_first[f + 1];
             const int grid = std::max(1, std::min(t1 - t0, b->grid));
-            VG_TRY(launch_tiles(b, kLin, b->d_poses, t0, t1, grid, nullptr, nullptr, 0, f, f + 1));
-            VG_TRY(launch_reduce(b, kLin, b->d_poses, (int32_t)f, (int32_t)f + 1, b->d_out, b->d_inliers, nullptr,
-                                 nullptr, nullptr));
+            const Workspace ws = batch_ws(b);
+            VG_TRY(launch_tiles(b, ws, kLin, b->d_poses, t0, t1, grid, nullptr, nullptr, 0, f, f + 1));
+            VG_TRY(launch_reduce(b, ws, kLin, b->d_poses, (int32_t)f, (int32_t)f + 1, b->d_out, b->d_inliers,
+                                 nullptr, nullptr, nullptr));
             VG_HIP(hipMemcpyAsync(b->h_out + kOutRow * f, b->d_out + kOutRow * f, sizeof(double) * kOutRow,
                                   hipMemcpyDeviceToHost, st));
             VG_HIP(hipMemcpyAsync(b->h_inliers + b->L * f, b->d_inliers + b->L * f, sizeof(int64_t) * b->L,
@@ -770,8 +805,12 @@ void free_batch(vg_batch* b) {
     dfree(b->d_posef);
     dfree(b->d_out);
     dfree(b->d_inliers);
+    dfree(b->d_work);
     dfree(b->d_e);
     dfree(b->d_lm);
+    dfree(b->d_shared);
+    dfree(b->d_slab_off);
+    dfree(b->d_gslab);
     hfree(b->h_poses);
     hfree(b->h_out);
     hfree(b->h_inliers);
@@ -809,6 +848,18 @@ extern "C" vg_status vg_create_factor_batch(vg_context* ctx, int64_t F, vg_sourc
     int bpc = o.blocks_per_cu ? o.blocks_per_cu : default_blocks_per_cu(block);
     if (!valid_shape(block, tile, bpc)) return invalid("invalid launch shape (block 64/128/256/512, tile a multiple of 64 up to 8192)");
     if (o.tile_order < 0 || o.tile_order > 2) return invalid("tile_order must be 0, 1 or 2");
+    if (o.precision == kC32) {
+        for (int64_t f = 0; f < F; ++f)
+            if (src[f]->extent > kMaxCompensatedExtent) {
+                char msg[320];
+                std::snprintf(msg, sizeof msg,
+                              "factor %lld: source spans %.1f m from its origin; the compensated FP32 mode keeps "
+                              "lever arms in FP32 and is limited to %.0f m (relative error of b above 1e-5 "
+                              "beyond); use VG_FP64 or split the cloud",
+                              (long long)f, src[f]->extent, kMaxCompensatedExtent);
+                return invalid(msg);
+            }
+    }
     VG_HIP(hipSetDevice(ctx->device));
     auto* b = new vg_batch();
     b->ctx = ctx;
@@ -833,10 +884,38 @@ extern "C" vg_status vg_create_factor_batch(vg_context* ctx, int64_t F, vg_sourc
         b->total_points += src[f]->n;
     }
     b->grad_rows = rows;
+    // sources used by several factors: each such factor writes its own point-gradient
+    // rows, summed per source in factor order (the sources in order of first use)
+    std::map<const vg_source*, size_t> shared_idx;
     for (int64_t f = 0; f < F; ++f) {
         fill_factor(b, f, target_viewpoints);
         b->h_fac[f].grad_offset = seen[src[f]].first;
-        b->h_fac[f].grad_exclusive = seen[src[f]].second == 1 ? 1 : 0;
+        b->h_fac[f].grad_slab = -1;
+        if (seen[src[f]].second > 1 && shared_idx.find(src[f]) == shared_idx.end()) {
+            shared_idx[src[f]] = b->h_shared.size();
+            SharedSrc q{};
+            q.row0 = b->shared_rows;
+            q.n = src[f]->n;
+            q.grad_offset = seen[src[f]].first;
+            b->h_shared.push_back(q);
+            b->shared_rows += src[f]->n;
+        }
+        b->max_source_extent = std::max(b->max_source_extent, src[f]->extent);
+    }
+    if (!b->h_shared.empty()) {
+        std::vector<std::vector<int64_t>> per(b->h_shared.size());
+        for (int64_t f = 0; f < F; ++f) {
+            auto it = shared_idx.find(src[f]);
+            if (it == shared_idx.end()) continue;
+            b->h_fac[f].grad_slab = b->slab_rows;
+            per[it->second].push_back(b->slab_rows);
+            b->slab_rows += src[f]->n;
+        }
+        for (size_t k = 0; k < per.size(); ++k) {
+            b->h_shared[k].f0 = (int32_t)b->h_slab_off.size();
+            b->h_slab_off.insert(b->h_slab_off.end(), per[k].begin(), per[k].end());
+            b->h_shared[k].f1 = (int32_t)b->h_slab_off.size();
+        }
     }
     b->block = block;
     b->tile_points = tile;
@@ -862,6 +941,20 @@ extern "C" vg_status vg_create_factor_batch(vg_context* ctx, int64_t F, vg_sourc
         if ((st = dev_alloc(&b->d_posef, 16 * F)) != VG_OK) break;
         if ((st = dev_alloc(&b->d_out, kOutRow * F)) != VG_OK) break;
         if ((st = dev_alloc(&b->d_inliers, (size_t)L * F)) != VG_OK) break;
+        if ((st = dev_alloc(&b->d_work, (size_t)kWork * F)) != VG_OK) break;
+        if (!b->h_shared.empty()) {
+            if ((st = dev_alloc(&b->d_shared, b->h_shared.size())) != VG_OK) break;
+            if ((st = dev_alloc(&b->d_slab_off, b->h_slab_off.size())) != VG_OK) break;
+            hipError_t e1 = hipMemcpyAsync(b->d_shared, b->h_shared.data(), sizeof(SharedSrc) * b->h_shared.size(),
+                                           hipMemcpyHostToDevice, ctx->stream);
+            if (e1 == hipSuccess)
+                e1 = hipMemcpyAsync(b->d_slab_off, b->h_slab_off.data(), sizeof(int64_t) * b->h_slab_off.size(),
+                                    hipMemcpyHostToDevice, ctx->stream);
+            if (e1 != hipSuccess) {
+                st = hip_fail(e1, "shared-source table upload");
+                break;
+            }
+        }
         if ((st = dev_alloc(&b->d_e, F)) != VG_OK) break;
         if ((st = dev_alloc(&b->d_lm, 32 * F)) != VG_OK) break;
         if ((st = host_alloc(&b->h_poses, 12 * F)) != VG_OK) break;
@@ -874,6 +967,7 @@ extern "C" vg_status vg_create_factor_batch(vg_context* ctx, int64_t F, vg_sourc
             break;
         }
         if ((st = launch_zero(ctx, b->d_counter, 64 * sizeof(uint32_t))) != VG_OK) break;
+        if ((st = launch_zero(ctx, b->d_work, sizeof(int64_t) * kWork * F)) != VG_OK) break;
         st = upload_schedule(b);
     } while (0);
     if (st != VG_OK) {
@@ -965,9 +1059,10 @@ extern "C" vg_status vg_overlap(vg_batch* b, const double* poses, double* overla
     std::memcpy(b->h_poses, poses, sizeof(double) * 12 * b->F);
     VG_HIP(hipMemcpyAsync(b->d_poses, b->h_poses, sizeof(double) * 12 * b->F, hipMemcpyHostToDevice, st));
     const int32_t nt = (int32_t)b->h_tiles.size();
-    VG_TRY(launch_tiles(b, kCount, b->d_poses, 0, nt, b->grid, nullptr, nullptr, 0, 0, b->F));
+    const Workspace ws = batch_ws(b);
+    VG_TRY(launch_tiles(b, ws, kCount, b->d_poses, 0, nt, b->grid, nullptr, nullptr, 0, 0, b->F));
     // the per-level fractions land in d_out (F x L <= F x 43)
-    VG_TRY(launch_reduce(b, kCount, b->d_poses, 0, (int32_t)b->F, b->d_out, nullptr, nullptr, nullptr, nullptr));
+    VG_TRY(launch_reduce(b, ws, kCount, b->d_poses, 0, (int32_t)b->F, b->d_out, nullptr, nullptr, nullptr, nullptr));
     VG_HIP(hipMemcpyAsync(b->h_out, b->d_out, sizeof(double) * b->L * b->F, hipMemcpyDeviceToHost, st));
     VG_HIP(hipStreamSynchronize(st));
     std::memcpy(overlap, b->h_out, sizeof(double) * b->L * b->F);
@@ -998,11 +1093,27 @@ extern "C" vg_status vg_backward_async(vg_batch* b, const double* d_poses, const
         return invalid("d_poses, d_grad_e or d_grad_xi is NULL");
     if (points_dtype != 0 && points_dtype != 1) return invalid("points_dtype must be 0 or 1");
     VG_HIP(hipSetDevice(b->ctx->device));
+    if (d_grad_points && b->slab_rows > 0) {
+        // per-factor rows of the shared sources (allocated on first use, kept with the batch)
+        const size_t need = (size_t)b->slab_rows * 3 * (points_dtype ? 8 : 4);
+        if (b->gslab_bytes < need) {
+            VG_HIP(hipStreamSynchronize(b->ctx->stream));
+            dfree(b->d_gslab);
+            b->d_gslab = nullptr;
+            b->gslab_bytes = 0;
+            unsigned char* p = nullptr;
+            VG_TRY(dev_alloc(&p, need));
+            b->d_gslab = p;
+            b->gslab_bytes = need;
+        }
+    }
     if (d_grad_points)
         VG_TRY(launch_zero(b->ctx, d_grad_points, (size_t)b->grad_rows * 3 * (points_dtype ? 8 : 4)));
     const int32_t nt = (int32_t)b->h_tiles.size();
-    VG_TRY(launch_tiles(b, kBwd, d_poses, 0, nt, b->grid, d_grad_e, d_grad_points, points_dtype, 0, b->F));
-    return launch_reduce(b, kBwd, d_poses, 0, (int32_t)b->F, nullptr, nullptr, d_grad_e, d_jr, d_grad_xi);
+    const Workspace ws = batch_ws(b);
+    VG_TRY(launch_tiles(b, ws, kBwd, d_poses, 0, nt, b->grid, d_grad_e, d_grad_points, points_dtype, 0, b->F));
+    VG_TRY(launch_grad_combine(b, d_grad_points, points_dtype));
+    return launch_reduce(b, ws, kBwd, d_poses, 0, (int32_t)b->F, nullptr, nullptr, d_grad_e, d_jr, d_grad_xi);
 }
 
 extern "C" vg_status vg_se3_retract_async(vg_context* ctx, int64_t F, const double* d_T0, const double* d_xi,
@@ -1013,6 +1124,35 @@ extern "C" vg_status vg_se3_retract_async(vg_context* ctx, int64_t F, const doub
     if (F > 0 && (d_T0 == nullptr || d_xi == nullptr || d_T == nullptr)) return invalid("NULL pointer");
     VG_HIP(hipSetDevice(ctx->device));
     return launch_se3_retract(ctx, F, d_T0, d_xi, d_T, d_jr);
+}
+
+namespace {
+
+// One Levenberg-Marquardt iteration for every factor, stream-ordered: linearize
+// at d_poses, propose T Exp(delta) from (H + lambda diag H) delta = -b, evaluate
+// the proposal, accept or reject it (lambda / 10 or x 10).  e at the input poses
+// and the decision go to column `col` of d_e / d_acc (rows of `stride`).
+vg_status lm_step(vg_batch* b, double* d_poses, double* d_lambda, double* d_e, int32_t* d_acc, int32_t stride,
+                  int32_t col) {
+    const int64_t F = b->F;
+    double* cand = b->d_lm + F;                              // 12 per factor
+    double* e_new = b->d_lm + 13 * F;                        // 1 per factor
+    int32_t* valid = reinterpret_cast<int32_t*>(b->d_lm + 14 * F);
+    VG_TRY(run_linearize_device(b, d_poses, b->d_out, nullptr));
+    VG_TRY(launch_lm_propose(b, b->d_out, d_lambda, d_poses, cand, valid));
+    VG_TRY(run_evaluate_device(b, cand, e_new));
+    return launch_lm_accept(b, b->d_out, e_new, d_lambda, d_poses, cand, valid, d_e, d_acc, stride, col);
+}
+
+}  // namespace
+
+extern "C" vg_status vg_lm_step_async(vg_batch* b, double* d_poses, double* d_lambda, double* d_e,
+                                      int32_t* d_accepted) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    if (d_poses == nullptr || d_lambda == nullptr) return invalid("d_poses or d_lambda is NULL");
+    VG_HIP(hipSetDevice(b->ctx->device));
+    return lm_step(b, d_poses, d_lambda, d_e, d_accepted, 1, 0);
 }
 
 extern "C" vg_status vg_lm_run(vg_batch* b, const double* poses_in, int32_t iters, double lambda0, double* poses_out,
@@ -1026,9 +1166,7 @@ extern "C" vg_status vg_lm_run(vg_batch* b, const double* poses_in, int32_t iter
     VG_HIP(hipSetDevice(b->ctx->device));
     hipStream_t st = b->ctx->stream;
     const int64_t F = b->F;
-    double* state = b->d_lm;                 // 4 per factor
-    double* cand = b->d_lm + 4 * F;          // 12 per factor
-    double* e_new = b->d_lm + 16 * F;        // 1 per factor
+    double* lambda = b->d_lm;                // 1 per factor
     int32_t* d_acc = nullptr;
     double* d_eh = nullptr;
     VG_TRY(dev_alloc(&d_acc, (size_t)F * std::max(iters, 1)));
@@ -1044,13 +1182,8 @@ extern "C" vg_status vg_lm_run(vg_batch* b, const double* poses_in, int32_t iter
             rc = hip_fail(e, "pose upload");
             break;
         }
-        if ((rc = launch_lm_init(b, state, lambda0)) != VG_OK) break;
-        for (int32_t it = 0; it < iters && rc == VG_OK; ++it) {
-            if ((rc = run_linearize_device(b, b->d_poses, b->d_out, nullptr)) != VG_OK) break;
-            if ((rc = launch_lm_propose(b, b->d_out, state, b->d_poses, cand)) != VG_OK) break;
-            if ((rc = run_evaluate_device(b, cand, e_new)) != VG_OK) break;
-            rc = launch_lm_accept(b, e_new, state, b->d_poses, cand, d_acc, d_eh, it, iters);
-        }
+        if ((rc = launch_fill(b->ctx, lambda, F, lambda0)) != VG_OK) break;
+        for (int32_t it = 0; it < iters && rc == VG_OK; ++it) rc = lm_step(b, b->d_poses, lambda, d_eh, d_acc, iters, it);
         if (rc != VG_OK) break;
         std::vector<int32_t> ha((size_t)F * std::max(iters, 1));
         std::vector<double> he((size_t)F * std::max(iters, 1));
@@ -1071,6 +1204,23 @@ extern "C" vg_status vg_lm_run(vg_batch* b, const double* poses_in, int32_t iter
     dfree(d_acc);
     dfree(d_eh);
     return rc;
+}
+
+extern "C" vg_status vg_batch_work(vg_batch* b, int64_t* walked_points, int64_t* walked_chunks, int64_t* lookups) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    VG_HIP(hipSetDevice(b->ctx->device));
+    std::vector<int64_t> w((size_t)kWork * b->F);
+    VG_HIP(hipMemcpyAsync(w.data(), b->d_work, sizeof(int64_t) * w.size(), hipMemcpyDeviceToHost, b->ctx->stream));
+    VG_HIP(hipStreamSynchronize(b->ctx->stream));
+    for (int64_t f = 0; f < b->F; ++f) {
+        const int64_t* r = w.data() + kWork * f;
+        if (walked_points) walked_points[f] = r[0];
+        if (walked_chunks) walked_chunks[f] = r[1];
+        if (lookups)
+            for (int l = 0; l < b->L; ++l) lookups[(int64_t)b->L * f + l] = r[2 + l];
+    }
+    return VG_OK;
 }
 
 extern "C" vg_status vg_correspondences(vg_batch* b, const double* pose, int64_t factor, int64_t* keys,
@@ -1120,11 +1270,11 @@ vg_status time_device(vg_batch* b, int reps, float* ms_tiles, float* ms_reduce) 
     vg_status rc = run_linearize_device(b, b->d_poses, b->d_out, b->d_inliers);   // warm-up
     for (int r = 0; r < reps && rc == VG_OK; ++r) {
         (void)hipEventRecord(ev[3 * r], st);
-        rc = launch_tiles(b, kLin, b->d_poses, 0, nt, b->grid, nullptr, nullptr, 0, 0, b->F);
+        rc = launch_tiles(b, batch_ws(b), kLin, b->d_poses, 0, nt, b->grid, nullptr, nullptr, 0, 0, b->F);
         (void)hipEventRecord(ev[3 * r + 1], st);
         if (rc == VG_OK)
-            rc = launch_reduce(b, kLin, b->d_poses, 0, (int32_t)b->F, b->d_out, b->d_inliers, nullptr, nullptr,
-                               nullptr);
+            rc = launch_reduce(b, batch_ws(b), kLin, b->d_poses, 0, (int32_t)b->F, b->d_out, b->d_inliers, nullptr,
+                               nullptr, nullptr);
         (void)hipEventRecord(ev[3 * r + 2], st);
     }
     hipError_t e = hipStreamSynchronize(st);

@@ -153,6 +153,7 @@ struct TileShared {
     float vc[kMaxTileChunks * 3];      // anchor - T^-1 c (surface validation)
     int32_t live[kMaxTileChunks];      // the chunks the waves walk, in chunk order
     int32_t nlive;
+    int32_t walked;                    // source points in those chunks
     uint8_t reach[kMaxTileChunks];     // chunk can reach a level's key box
 };
 
@@ -164,6 +165,7 @@ struct TileShared {
 // 64 are queued, so at most 127 are ever held.  The FP64 mode leaves x, y, z
 // unused (its drain re-reads the FP64 position).
 constexpr int kQueue = 128;
+static_assert(kMaxTileChunks * kChunk < 65536, "per-tile counts are packed in 16 bits");
 struct HitQueue {
     float x[kQueue], y[kQueue], z[kQueue];   // point offset from its chunk anchor (compensated mode)
     int32_t pt[kQueue];                      // point index in the source (internal order)
@@ -357,6 +359,74 @@ __device__ __forceinline__ bool chunk_reaches(const FactorDesc* __restrict__ Fp,
     return reach;
 }
 
+// Gradient of point i (internal order) of a factor: a source used by this
+// factor only is written in place (caller order); a source shared with other
+// factors gets this factor's own rows in the per-factor buffer, summed per
+// source in factor order by k_grad_combine, so the result does not depend on
+// which workgroup finished first.
+__device__ __forceinline__ void write_point_grad(const FactorDesc* __restrict__ Fp, int64_t i, void* grad_points,
+                                                 void* grad_slab, int32_t dtype, double g0, double g1, double g2) {
+    const bool own = Fp->grad_slab < 0;
+    const int64_t row = (own ? Fp->grad_offset : Fp->grad_slab) + Fp->perm[i];
+    void* base = own ? grad_points : grad_slab;
+    if (dtype == 0) {
+        float* g = (float*)base + 3 * row;
+        g[0] = (float)g0;
+        g[1] = (float)g1;
+        g[2] = (float)g2;
+    } else {
+        double* g = (double*)base + 3 * row;
+        g[0] = g0;
+        g[1] = g1;
+        g[2] = g2;
+    }
+}
+
+// Point-gradient rows of the shared sources: row k of source s is the sum over
+// its factors, in factor order, of their rows k in the per-factor buffer
+// (FP64 sums of the per-factor values).  One thread per row.
+__global__ void k_grad_combine(const SharedSrc* __restrict__ ss, int32_t S, int64_t rows,
+                               const int64_t* __restrict__ slab_off, const void* __restrict__ slab,
+                               void* __restrict__ out, int32_t dtype) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    int lo = 0, hi = S - 1;   // last shared source whose rows start at or before r
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ss[mid].row0 <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    const SharedSrc q = ss[lo];
+    const int64_t k = r - q.row0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int32_t j = q.f0; j < q.f1; ++j) {
+        const int64_t o = 3 * (slab_off[j] + k);
+        if (dtype == 0) {
+            const float* g = (const float*)slab + o;
+            a0 += (double)g[0];
+            a1 += (double)g[1];
+            a2 += (double)g[2];
+        } else {
+            const double* g = (const double*)slab + o;
+            a0 += g[0];
+            a1 += g[1];
+            a2 += g[2];
+        }
+    }
+    const int64_t w = 3 * (q.grad_offset + k);
+    if (dtype == 0) {
+        float* g = (float*)out + w;
+        g[0] = (float)a0;
+        g[1] = (float)a1;
+        g[2] = (float)a2;
+    } else {
+        double* g = (double*)out + w;
+        g[0] = a0;
+        g[1] = a1;
+        g[2] = a2;
+    }
+}
+
 // Pose staging: FP32 copies of every factor's R and t (16 floats per factor),
 // read by the tile kernel through uniform (scalar) loads.
 __global__ void k_stage_poses(int64_t F, const double* __restrict__ poses, float* __restrict__ posef) {
@@ -371,7 +441,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
     const FactorDesc* __restrict__ fac, const Tile* __restrict__ tiles, int32_t t_begin, int32_t t_end,
     const double* __restrict__ poses, const float* __restrict__ posef, double* __restrict__ partials,
     uint32_t* __restrict__ counter, int32_t validate, const double* __restrict__ grad_e,
-    void* __restrict__ grad_points, int32_t points_dtype, int32_t interleave) {
+    void* __restrict__ grad_points, void* __restrict__ grad_slab, int32_t points_dtype, int32_t interleave) {
     using T = typename PT<PREC>::T;
     constexpr int NW = BLOCK / 64;
     constexpr bool KAHAN = KH && (PREC == kC32);
@@ -502,24 +572,36 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
         // the list of chunks to walk (kept in chunk order)
         if (wave == 0) {
             int cnt = 0;
+            int32_t pts = 0;   // per lane: points of the chunks this lane kept
             for (int base = 0; base < tile.nchunks; base += 64) {
                 const int c = base + lane;
                 bool keep = c < tile.nchunks;
                 if constexpr (SKIP) keep = keep && sh.reach[c];
                 const uint64_t m = __ballot(keep);
-                if (keep)
+                if (keep) {
                     sh.live[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = c;
+                    pts += (int32_t)min<int64_t>(kChunk, n - (int64_t)(tile.chunk0 + c) * kChunk);
+                }
                 cnt += __popcll(m);
             }
-            if (lane == 0) sh.nlive = cnt;
+            pts = wave_sum(pts);
+            if (lane == 0) {
+                sh.nlive = cnt;
+                sh.walked = pts;
+            }
         }
         __syncthreads();
         const int nlive = __builtin_amdgcn_readfirstlane(sh.nlive);
         // ---------------------------------------------------------------- per-point work
         Acc<T, KAHAN, NT> acc;
         acc.zero();
-        int32_t inl[kMaxLevels] = {0, 0, 0, 0};   // per lane (wave totals in the compacted paths)
+        // points with a voxel and table lookups per level: per lane, or in the
+        // compacted paths wave-uniform totals packed two levels per word (level l
+        // in bits 16 (l % 2) of word l / 2; a tile has fewer than 65536 points)
+        int32_t inl[kMaxLevels] = {0, 0, 0, 0};
+        int32_t prb[kMaxLevels] = {0, 0, 0, 0};
+        uint32_t inl2[2] = {0u, 0u}, prb2[2] = {0u, 0u};
         double ge = 0.0;
         if constexpr (MODE == kBwd) ge = grad_e[tile.factor];
 
@@ -571,10 +653,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         kq[a] = (int32_t)k;
                     }
                     int32_t v = -1;
+                    prb2[l >> 1] += (uint32_t)__popcll(__ballot(in)) << (16 * (l & 1));
                     if (in) v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
                     const bool hit = v >= 0;
                     const uint64_t mask = __ballot(hit);
-                    inl[l] += __popcll(mask);   // wave-uniform count
+                    inl2[l >> 1] += (uint32_t)__popcll(mask) << (16 * (l & 1));
                     const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
                     if (hit) {
@@ -624,10 +707,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         kq[a] = (int32_t)((uint32_t)sh.kb[3 * c + a] << pl.log2scale) + floor_i32(yl[a] * pl.inv_r);
                         in &= (uint32_t)(kq[a] - pl.kbox0[a]) <= pl.kboxw[a];
                     }
+                    prb2[l >> 1] += (uint32_t)__popcll(__ballot(in)) << (16 * (l & 1));
                     if (in) v = lookup(pl.slots, pl.log2cap, kq[0], kq[1], kq[2]);
                     const bool hit = v >= 0;
                     const uint64_t mask = __ballot(hit);
-                    inl[l] += __popcll(mask);   // wave-uniform count
+                    inl2[l >> 1] += (uint32_t)__popcll(mask) << (16 * (l & 1));
                     const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
                     if (hit) {
@@ -707,16 +791,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
             }
             if (!vis) {
                 if constexpr (MODE == kBwd) {
-                    if (grad_points != nullptr && Fp->grad_exclusive) {
-                        const int64_t row = Fp->grad_offset + Fp->perm[i];
-                        if (points_dtype == 0) {
-                            float* g = (float*)grad_points + 3 * row;
-                            g[0] = 0.f; g[1] = 0.f; g[2] = 0.f;
-                        } else {
-                            double* g = (double*)grad_points + 3 * row;
-                            g[0] = 0.0; g[1] = 0.0; g[2] = 0.0;
-                        }
-                    }
+                    if (grad_points != nullptr) write_point_grad(Fp, i, grad_points, grad_slab, points_dtype, 0.0, 0.0, 0.0);
                 }
                 continue;
             }
@@ -758,6 +833,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     }
                 }
                 if (!in) continue;
+                prb[l] += 1;
                 const int32_t v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
                 if (v < 0) continue;
                 inl[l] += 1;
@@ -849,31 +925,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 }
             }
             if constexpr (MODE == kBwd) {
-                if (grad_points != nullptr) {
-                    const int64_t row = Fp->grad_offset + Fp->perm[i];
-                    if (points_dtype == 0) {
-                        float* g = (float*)grad_points + 3 * row;
-                        const float g0 = (float)(ge * (double)gp[0]), g1 = (float)(ge * (double)gp[1]),
-                                    g2 = (float)(ge * (double)gp[2]);
-                        if (Fp->grad_exclusive) {
-                            g[0] = g0; g[1] = g1; g[2] = g2;
-                        } else {
-                            atomicAdd(g + 0, g0);
-                            atomicAdd(g + 1, g1);
-                            atomicAdd(g + 2, g2);
-                        }
-                    } else {
-                        double* g = (double*)grad_points + 3 * row;
-                        const double g0 = ge * (double)gp[0], g1 = ge * (double)gp[1], g2 = ge * (double)gp[2];
-                        if (Fp->grad_exclusive) {
-                            g[0] = g0; g[1] = g1; g[2] = g2;
-                        } else {
-                            atomicAdd(g + 0, g0);
-                            atomicAdd(g + 1, g1);
-                            atomicAdd(g + 2, g2);
-                        }
-                    }
-                }
+                if (grad_points != nullptr)
+                    write_point_grad(Fp, i, grad_points, grad_slab, points_dtype, ge * (double)gp[0],
+                                     ge * (double)gp[1], ge * (double)gp[2]);
             }
         }
         if constexpr (CMP) {
@@ -901,26 +955,33 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
         if constexpr (MODE != kBwd) {
 #pragma unroll
             for (int l = 0; l < kMaxLevels; ++l) {
-                const int32_t v = CMP ? inl[l] : wave_sum(inl[l]);
-                if (lane == 0) s_red[wave][kTerms + l] = (double)v;
+                const int32_t v = CMP ? (int32_t)((inl2[l >> 1] >> (16 * (l & 1))) & 0xFFFFu) : wave_sum(inl[l]);
+                const int32_t p = CMP ? (int32_t)((prb2[l >> 1] >> (16 * (l & 1))) & 0xFFFFu) : wave_sum(prb[l]);
+                if (lane == 0) {
+                    s_red[wave][kRowInl + l] = (double)v;
+                    s_red[wave][kRowProbe + l] = (double)p;
+                }
             }
         }
         __syncthreads();
         if (threadIdx.x < kRow) {
             const int k = threadIdx.x;
             double s = 0.0;
-            if constexpr (PREC == kN32) {
-                if (k < kTerms) {
-                    float sf = 0.f;
-                    for (int w = 0; w < NW; ++w) sf += (float)s_red[w][k];
-                    s = (double)sf;
-                } else {
-                    for (int w = 0; w < NW; ++w) s += s_red[w][k];
-                }
+            const bool inl_or_probe = (k >= kRowInl && k < kRowWalk) || (k >= kRowProbe && k < kRowChunks);
+            if (k == kRowWalk) {
+                s = (double)sh.walked;
+            } else if (k == kRowChunks) {
+                s = (double)nlive;
+            } else if (k >= kRowChunks + 1) {
+                s = 0.0;
+            } else if (PREC == kN32 && k < kTerms) {
+                float sf = 0.f;
+                for (int w = 0; w < NW; ++w) sf += (float)s_red[w][k];
+                s = (double)sf;
             } else {
                 for (int w = 0; w < NW; ++w) s += s_red[w][k];
             }
-            const bool used = (k < NT) || (MODE != kBwd && k >= kTerms);
+            const bool used = (k < NT) || (MODE != kBwd && inl_or_probe) || k == kRowWalk || k == kRowChunks;
             partials[(int64_t)t * kRow + k] = used ? s : 0.0;
         }
         __syncthreads();
@@ -936,7 +997,7 @@ __global__ __launch_bounds__(64) void k_reduce(const FactorDesc* __restrict__ fa
                                                const double* __restrict__ poses, double* __restrict__ out,
                                                int64_t* __restrict__ inliers, uint32_t* __restrict__ counter,
                                                const double* __restrict__ grad_e, const double* __restrict__ jr,
-                                               double* __restrict__ grad_xi) {
+                                               double* __restrict__ grad_xi, int64_t* __restrict__ work) {
     __shared__ double s[kRow];
     const int f = f0 + blockIdx.x;
     if (blockIdx.x == 0 && threadIdx.x < kParts) counter[threadIdx.x] = 0u;
@@ -951,7 +1012,7 @@ __global__ __launch_bounds__(64) void k_reduce(const FactorDesc* __restrict__ fa
                 sf += (float)v;
                 si += v;
             }
-            s[k] = (k >= kTerms) ? si : (double)sf;
+            s[k] = (k >= kTerms) ? si : (double)sf;   // counts are exact integers in FP64
         } else {
             double acc = 0.0;
             for (int32_t t = a; t < bnd; ++t) acc += partials[(int64_t)t * kRow + k];
@@ -963,6 +1024,14 @@ __global__ __launch_bounds__(64) void k_reduce(const FactorDesc* __restrict__ fa
     const FactorDesc& F = fac[f];
     const double* P = poses + 12 * f;
     const double* R = P;
+    if (work != nullptr && MODE != kBwd) {
+        int64_t* wr = work + (int64_t)kWork * f;
+        wr[0] = (int64_t)s[kRowWalk];
+        wr[1] = (int64_t)s[kRowChunks];
+        for (int l = 0; l < kMaxLevels; ++l) wr[2 + l] = (int64_t)s[kRowProbe + l];
+        wr[6] = 0;
+        wr[7] = 0;
+    }
     const double o[3] = {PREC == kC32 ? F.src_origin[0] : 0.0, PREC == kC32 ? F.src_origin[1] : 0.0,
                          PREC == kC32 ? F.src_origin[2] : 0.0};
     if constexpr (MODE == kEval) {
@@ -1126,14 +1195,14 @@ __global__ void k_fill_zero(uint32_t* p, int64_t n_words) {
 // ---------------------------------------------------------------- host launchers
 
 template <int MODE, int PREC, bool KH>
-static vg_status launch_tiles_t(vg_batch* b, const double* d_poses, int32_t t0, int32_t t1, int grid,
-                                const double* d_grad_e, void* d_grad_points, int points_dtype) {
+static vg_status launch_tiles_t(vg_batch* b, const Workspace& ws, const double* d_poses, int32_t t0, int32_t t1,
+                                int grid, const double* d_grad_e, void* d_grad_points, int points_dtype) {
     hipStream_t st = b->ctx->stream;
     const int v = b->opt.surface_validation;
 #define VG_LAUNCH(BS)                                                                                         \
-    k_tiles<MODE, PREC, BS, KH><<<grid, BS, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, b->d_posef,        \
-                                                     b->d_partials, b->d_counter, v, d_grad_e, d_grad_points,  \
-                                                     points_dtype, b->tile_order == 2 ? 1 : 0)
+    k_tiles<MODE, PREC, BS, KH><<<grid, BS, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, ws.posef,          \
+                                                     ws.partials, ws.counter, v, d_grad_e, d_grad_points,      \
+                                                     b->d_gslab, points_dtype, b->tile_order == 2 ? 1 : 0)
     switch (b->block) {
         case 64: VG_LAUNCH(64); break;
         case 128: VG_LAUNCH(128); break;
@@ -1145,25 +1214,27 @@ static vg_status launch_tiles_t(vg_batch* b, const double* d_poses, int32_t t0, 
     return VG_OK;
 }
 
-vg_status launch_tiles(vg_batch* b, int mode, const double* d_poses, int32_t t0, int32_t t1, int grid,
-                       const double* d_grad_e, void* d_grad_points, int points_dtype, int64_t f0, int64_t f1) {
+vg_status launch_tiles(vg_batch* b, const Workspace& ws, int mode, const double* d_poses, int32_t t0, int32_t t1,
+                       int grid, const double* d_grad_e, void* d_grad_points, int points_dtype, int64_t f0,
+                       int64_t f1) {
     if (grid < 1) grid = 1;
+    if (t1 <= t0) return VG_OK;
     if (b->opt.precision != kF64 && f1 > f0) {
         const int64_t nf = (f1 - f0) * 16;
         k_stage_poses<<<(int)((nf + 255) / 256), 256, 0, b->ctx->stream>>>(f1 - f0, d_poses + 12 * f0,
-                                                                          b->d_posef + 16 * f0);
+                                                                          ws.posef + 16 * f0);
         VG_HIP(hipGetLastError());
     }
     const int p = b->opt.precision;
     const bool kh = b->opt.lane_kahan != 0;
 #define VG_DISPATCH(M)                                                                                  \
     if (p == kC32 && kh)                                                                                \
-        return launch_tiles_t<M, kC32, true>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype); \
+        return launch_tiles_t<M, kC32, true>(b, ws, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype); \
     if (p == kC32)                                                                                      \
-        return launch_tiles_t<M, kC32, false>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype); \
+        return launch_tiles_t<M, kC32, false>(b, ws, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype); \
     if (p == kN32)                                                                                      \
-        return launch_tiles_t<M, kN32, false>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype); \
-    return launch_tiles_t<M, kF64, false>(b, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype);
+        return launch_tiles_t<M, kN32, false>(b, ws, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype); \
+    return launch_tiles_t<M, kF64, false>(b, ws, d_poses, t0, t1, grid, d_grad_e, d_grad_points, points_dtype);
     if (mode == kLin) { VG_DISPATCH(kLin) }
     if (mode == kEval) { VG_DISPATCH(kEval) }
     if (mode == kCount) { VG_DISPATCH(kCount) }
@@ -1172,25 +1243,36 @@ vg_status launch_tiles(vg_batch* b, int mode, const double* d_poses, int32_t t0,
 }
 
 template <int MODE, int PREC>
-static void reduce_t(vg_batch* b, const double* d_poses, int32_t f0, int32_t f1, double* d_out, int64_t* d_inl,
-                     const double* d_grad_e, const double* d_jr, double* d_grad_xi) {
-    k_reduce<MODE, PREC><<<f1 - f0, 64, 0, b->ctx->stream>>>(b->d_fac, b->d_tile_first, f0, b->d_partials, d_poses,
-                                                             d_out, d_inl, b->d_counter, d_grad_e, d_jr, d_grad_xi);
+static void reduce_t(vg_batch* b, const Workspace& ws, const double* d_poses, int32_t f0, int32_t f1, double* d_out,
+                     int64_t* d_inl, const double* d_grad_e, const double* d_jr, double* d_grad_xi) {
+    k_reduce<MODE, PREC><<<f1 - f0, 64, 0, b->ctx->stream>>>(b->d_fac, b->d_tile_first, f0, ws.partials, d_poses,
+                                                             d_out, d_inl, ws.counter, d_grad_e, d_jr, d_grad_xi,
+                                                             ws.work);
 }
 
-vg_status launch_reduce(vg_batch* b, int mode, const double* d_poses, int32_t f0, int32_t f1, double* d_out,
-                        int64_t* d_inliers, const double* d_grad_e, const double* d_jr, double* d_grad_xi) {
+vg_status launch_reduce(vg_batch* b, const Workspace& ws, int mode, const double* d_poses, int32_t f0, int32_t f1,
+                        double* d_out, int64_t* d_inliers, const double* d_grad_e, const double* d_jr,
+                        double* d_grad_xi) {
     if (f1 <= f0) return VG_OK;
     const int p = b->opt.precision;
 #define VG_R(M)                                                                               \
-    if (p == kC32) reduce_t<M, kC32>(b, d_poses, f0, f1, d_out, d_inliers, d_grad_e, d_jr, d_grad_xi); \
-    else if (p == kN32) reduce_t<M, kN32>(b, d_poses, f0, f1, d_out, d_inliers, d_grad_e, d_jr, d_grad_xi); \
-    else reduce_t<M, kF64>(b, d_poses, f0, f1, d_out, d_inliers, d_grad_e, d_jr, d_grad_xi);
+    if (p == kC32) reduce_t<M, kC32>(b, ws, d_poses, f0, f1, d_out, d_inliers, d_grad_e, d_jr, d_grad_xi); \
+    else if (p == kN32) reduce_t<M, kN32>(b, ws, d_poses, f0, f1, d_out, d_inliers, d_grad_e, d_jr, d_grad_xi); \
+    else reduce_t<M, kF64>(b, ws, d_poses, f0, f1, d_out, d_inliers, d_grad_e, d_jr, d_grad_xi);
     if (mode == kLin) { VG_R(kLin) }
     else if (mode == kEval) { VG_R(kEval) }
     else if (mode == kCount) { VG_R(kCount) }
     else { VG_R(kBwd) }
 #undef VG_R
+    VG_HIP(hipGetLastError());
+    return VG_OK;
+}
+
+vg_status launch_grad_combine(vg_batch* b, void* d_grad_points, int points_dtype) {
+    if (b->shared_rows == 0 || d_grad_points == nullptr) return VG_OK;
+    const int grid = (int)((b->shared_rows + 255) / 256);
+    k_grad_combine<<<grid, 256, 0, b->ctx->stream>>>(b->d_shared, (int32_t)b->h_shared.size(), b->shared_rows,
+                                                     b->d_slab_off, b->d_gslab, d_grad_points, points_dtype);
     VG_HIP(hipGetLastError());
     return VG_OK;
 }

@@ -23,8 +23,16 @@ constexpr int kBaseBits = 28;           // first-record index bits of a block en
 constexpr uint64_t kBaseMask = (1ull << kBaseBits) - 1;
 constexpr int64_t kMaxVoxels = (int64_t)kBaseMask - 1;  // so a valid entry word is never all ones
 constexpr uint64_t kEmpty = ~0ull;      // empty block-table entry
-constexpr int kRow = 32;                // partial row: 28 terms + 4 inlier counts
 constexpr int kTerms = 28;              // e, 21 upper-triangular H, 6 b
+// partial row of a tile (FP64): 28 terms, inliers per level, then the work the
+// tile did: source points walked (chunks not culled), table lookups per level
+// (point-levels inside the level's key box), chunks walked
+constexpr int kRowInl = kTerms;                  // 4: points with a voxel, per level
+constexpr int kRowWalk = kRowInl + 4;            // 1: source points walked
+constexpr int kRowProbe = kRowWalk + 1;          // 4: table lookups, per level
+constexpr int kRowChunks = kRowProbe + 4;        // 1: chunks walked
+constexpr int kRow = 40;
+constexpr int kWork = 8;                // per-factor work counts: walked points, walked chunks, lookups (4), 0, 0
 constexpr int kMaxTileChunks = 128;     // at most 8192 points per tile
 constexpr int kRec32 = 16;              // floats per compensated voxel record (64 B: 4 FP32 + 6 FP64)
 constexpr int kRecN = 12;               // floats per absolute-FP32 voxel record
@@ -71,11 +79,31 @@ struct FactorDesc {
     const int32_t* perm;     // internal index -> caller index
     int64_t n, n_pad;
     int64_t grad_offset;     // first row of this source in the concatenated point gradient
-    int32_t grad_exclusive;  // 1 if no other factor of the batch uses this source
+    int64_t grad_slab;       // -1 if no other factor of the batch uses this source; otherwise the
+                             //   first row of this factor's own rows in the per-factor gradient
+                             //   buffer, summed per source in factor order afterwards
     int32_t L;
+    int32_t pad_;
     double src_origin[3];    // o_s: the re-centring origin of the source
     double viewpoint[3];     // target viewpoint (target frame) for surface validation
     LevelDesc lv[kMaxLevels];
+};
+
+// A source used by several factors of a batch: its rows of the point gradient
+// are the sum, in factor order, of those factors' rows in the per-factor buffer.
+struct SharedSrc {
+    int64_t row0;            // first of its rows among all shared sources' rows
+    int64_t n;               // points
+    int64_t grad_offset;     // first row in the concatenated point gradient
+    int32_t f0, f1;          // its factors' entries [f0, f1) in the slab-offset list
+};
+
+// Device buffers one launch of the tile kernel and reduction works in.
+struct Workspace {
+    double* partials;        // n_tiles x kRow
+    uint32_t* counter;       // kParts tile counters (zero before the first launch)
+    float* posef;            // F x 16 staged FP32 poses
+    int64_t* work;           // F x kWork work counts, or nullptr
 };
 
 struct Tile {
@@ -112,6 +140,7 @@ struct vg_context {
     void* ws = nullptr;          // grow-only device workspace of the preprocessing calls
     size_t ws_bytes = 0;
     int num_cu = 0;
+    void* scratch = nullptr;     // this device's fixed scratch array (device address), or nullptr
     std::string arch;
     std::string name;
     uint32_t magic = 0;
@@ -141,6 +170,7 @@ struct vg_source {
     double* cov64 = nullptr;
     double* nrm64 = nullptr;
     int32_t* perm = nullptr;   // internal -> caller
+    double extent = 0.0;       // upper bound of |mu - origin| over its points (m), from the chunk bounds
     int users = 0;
     uint32_t magic = 0;
 };
@@ -187,8 +217,19 @@ struct vg_batch {
     float* d_posef = nullptr;       // F x 16 staged FP32 poses
     double* d_out = nullptr;        // F x 43
     int64_t* d_inliers = nullptr;   // F x L
+    int64_t* d_work = nullptr;      // F x kWork work counts of the last linearize / evaluate / overlap
     double* d_e = nullptr;          // F (evaluate)
     double* d_lm = nullptr;         // LM scratch
+    // sources shared by several factors (deterministic point gradients)
+    std::vector<vg::SharedSrc> h_shared;
+    std::vector<int64_t> h_slab_off;     // per shared source, its factors' slab rows, factor order
+    int64_t slab_rows = 0;
+    int64_t shared_rows = 0;
+    vg::SharedSrc* d_shared = nullptr;
+    int64_t* d_slab_off = nullptr;
+    void* d_gslab = nullptr;             // per-factor point gradients (grown on first use)
+    size_t gslab_bytes = 0;
+    double max_source_extent = 0.0;      // largest |mu - o_s| over the batch's sources (m)
     // pinned host staging (one upload, one download)
     double* h_poses = nullptr;
     double* h_out = nullptr;
@@ -231,20 +272,31 @@ vg_status set_source_points(vg_context* ctx, vg_source* s, const void* d_xyz, in
 
 // launch the tile kernel over tiles [t0, t1) and the reduction over factors [f0, f1)
 // f0, f1: the factors those tiles belong to (their poses are staged to FP32 first)
-vg_status launch_tiles(vg_batch* b, int mode, const double* d_poses, int32_t t0, int32_t t1, int grid,
-                       const double* d_grad_e, void* d_grad_points, int points_dtype, int64_t f0, int64_t f1);
-vg_status launch_reduce(vg_batch* b, int mode, const double* d_poses, int32_t f0, int32_t f1, double* d_out,
-                        int64_t* d_inliers, const double* d_grad_e, const double* d_jr, double* d_grad_xi);
+// ws: the buffers of the launch (the batch's own, or a caller-provided scratch)
+vg_status launch_tiles(vg_batch* b, const Workspace& ws, int mode, const double* d_poses, int32_t t0, int32_t t1,
+                       int grid, const double* d_grad_e, void* d_grad_points, int points_dtype, int64_t f0,
+                       int64_t f1);
+vg_status launch_reduce(vg_batch* b, const Workspace& ws, int mode, const double* d_poses, int32_t f0, int32_t f1,
+                        double* d_out, int64_t* d_inliers, const double* d_grad_e, const double* d_jr,
+                        double* d_grad_xi);
+// rows of shared sources: sum of their factors' per-factor rows in factor order
+vg_status launch_grad_combine(vg_batch* b, void* d_grad_points, int points_dtype);
 vg_status launch_correspondences(vg_batch* b, const double* d_pose, int64_t factor, int64_t* d_keys,
                                  int32_t* d_found);
 vg_status launch_zero(vg_context* ctx, void* d_ptr, size_t bytes);
 vg_status launch_se3_retract(vg_context* ctx, int64_t F, const double* d_T0, const double* d_xi, double* d_T,
                              double* d_jr);
-vg_status launch_lm_propose(vg_batch* b, const double* d_out, double* d_state, double* d_poses,
-                            double* d_cand);
-vg_status launch_lm_init(vg_batch* b, double* d_state, double lambda0);
-vg_status launch_lm_accept(vg_batch* b, const double* d_e_new, double* d_state, double* d_poses,
-                           const double* d_cand, int32_t* d_accepted, double* d_e_hist, int32_t it,
-                           int32_t iters);
+// LM on the device: propose solves (H + lambda diag H) delta = -b from the
+// linearization rows d_out and writes T Exp(delta) to d_cand (d_valid = 0 and
+// d_cand = T where the damped matrix is not SPD); accept keeps the candidate
+// iff it is valid and e decreases (lambda / 10), else keeps T (lambda x 10),
+// writing e at T and the decision to d_e / d_accepted at column `col` of rows
+// of length `stride` (either may be nullptr).
+vg_status launch_lm_propose(vg_batch* b, const double* d_out, const double* d_lambda, const double* d_poses,
+                            double* d_cand, int32_t* d_valid);
+vg_status launch_lm_accept(vg_batch* b, const double* d_out, const double* d_e_new, double* d_lambda,
+                           double* d_poses, const double* d_cand, const int32_t* d_valid, double* d_e,
+                           int32_t* d_accepted, int32_t stride, int32_t col);
+vg_status launch_fill(vg_context* ctx, double* d_ptr, int64_t n, double v);
 
 }  // namespace vg

@@ -142,17 +142,17 @@ __device__ bool lm_solve(const double* row, double lambda, double delta[6]) {
     return true;
 }
 
-// state per factor: [lambda, e at T, proposal valid]
-__global__ void k_lm_propose(int64_t F, const double* __restrict__ out, double* __restrict__ state,
-                             const double* __restrict__ poses, double* __restrict__ cand) {
+// Proposal of one damped step per factor: delta from (H + lambda diag H) delta = -b
+// (FP64 Cholesky) at the linearization rows, candidate T Exp(delta).  A matrix
+// that is not SPD leaves the candidate at T and marks it invalid.
+__global__ void k_lm_propose(int64_t F, const double* __restrict__ out, const double* __restrict__ lambda,
+                             const double* __restrict__ poses, double* __restrict__ cand, int32_t* __restrict__ valid) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= F) return;
     const double* row = out + (int64_t)kOutRow * f;
-    double* s = state + 4 * f;
-    s[1] = row[0];
     double delta[6], T[12], E[12], C[12];
     for (int k = 0; k < 12; ++k) T[k] = poses[12 * f + k];
-    const bool ok = lm_solve(row, s[0], delta);
+    const bool ok = lm_solve(row, lambda[f], delta);
     if (ok) {
         se3_exp(delta, E);
         pose_mul(T, E, C);
@@ -160,33 +160,32 @@ __global__ void k_lm_propose(int64_t F, const double* __restrict__ out, double* 
         for (int k = 0; k < 12; ++k) C[k] = T[k];
     }
     for (int k = 0; k < 12; ++k) cand[12 * f + k] = C[k];
-    s[2] = ok ? 1.0 : 0.0;
+    valid[f] = ok ? 1 : 0;
 }
 
-__global__ void k_lm_accept(int64_t F, const double* __restrict__ e_new, double* __restrict__ state,
-                            double* __restrict__ poses, const double* __restrict__ cand, int32_t* __restrict__ accepted,
-                            double* __restrict__ e_hist, int32_t it, int32_t iters) {
+// Accept the candidate iff it is valid and its error is below the error at T
+// (then lambda / 10), else keep T (lambda x 10).  Records e at T and the decision.
+__global__ void k_lm_accept(int64_t F, const double* __restrict__ out, const double* __restrict__ e_new,
+                            double* __restrict__ lambda, double* __restrict__ poses, const double* __restrict__ cand,
+                            const int32_t* __restrict__ valid, double* __restrict__ e_out,
+                            int32_t* __restrict__ accepted, int32_t stride, int32_t col) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= F) return;
-    double* s = state + 4 * f;
-    const bool acc = (s[2] != 0.0) && (e_new[f] < s[1]);
+    const double e0 = out[(int64_t)kOutRow * f];
+    const bool acc = (valid[f] != 0) && (e_new[f] < e0);
     if (acc) {
         for (int k = 0; k < 12; ++k) poses[12 * f + k] = cand[12 * f + k];
-        s[0] /= 10.0;
+        lambda[f] /= 10.0;
     } else {
-        s[0] *= 10.0;
+        lambda[f] *= 10.0;
     }
-    accepted[(int64_t)iters * f + it] = acc ? 1 : 0;
-    e_hist[(int64_t)iters * f + it] = s[1];
+    if (accepted != nullptr) accepted[(int64_t)stride * f + col] = acc ? 1 : 0;
+    if (e_out != nullptr) e_out[(int64_t)stride * f + col] = e0;
 }
 
-__global__ void k_lm_init(int64_t F, double* __restrict__ state, double lambda0) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= F) return;
-    state[4 * f + 0] = lambda0;
-    state[4 * f + 1] = 0.0;
-    state[4 * f + 2] = 0.0;
-    state[4 * f + 3] = 0.0;
+__global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 vg_status launch_se3_retract(vg_context* ctx, int64_t F, const double* d_T0, const double* d_xi, double* d_T,
@@ -197,22 +196,26 @@ vg_status launch_se3_retract(vg_context* ctx, int64_t F, const double* d_T0, con
     return VG_OK;
 }
 
-vg_status launch_lm_propose(vg_batch* b, const double* d_out, double* d_state, double* d_poses, double* d_cand) {
-    k_lm_propose<<<(int)((b->F + 63) / 64), 64, 0, b->ctx->stream>>>(b->F, d_out, d_state, d_poses, d_cand);
+vg_status launch_lm_propose(vg_batch* b, const double* d_out, const double* d_lambda, const double* d_poses,
+                            double* d_cand, int32_t* d_valid) {
+    k_lm_propose<<<(int)((b->F + 63) / 64), 64, 0, b->ctx->stream>>>(b->F, d_out, d_lambda, d_poses, d_cand,
+                                                                     d_valid);
     VG_HIP(hipGetLastError());
     return VG_OK;
 }
 
-vg_status launch_lm_accept(vg_batch* b, const double* d_e_new, double* d_state, double* d_poses,
-                           const double* d_cand, int32_t* d_accepted, double* d_e_hist, int32_t it, int32_t iters) {
-    k_lm_accept<<<(int)((b->F + 63) / 64), 64, 0, b->ctx->stream>>>(b->F, d_e_new, d_state, d_poses, d_cand,
-                                                                    d_accepted, d_e_hist, it, iters);
+vg_status launch_lm_accept(vg_batch* b, const double* d_out, const double* d_e_new, double* d_lambda,
+                           double* d_poses, const double* d_cand, const int32_t* d_valid, double* d_e,
+                           int32_t* d_accepted, int32_t stride, int32_t col) {
+    k_lm_accept<<<(int)((b->F + 63) / 64), 64, 0, b->ctx->stream>>>(b->F, d_out, d_e_new, d_lambda, d_poses, d_cand,
+                                                                    d_valid, d_e, d_accepted, stride, col);
     VG_HIP(hipGetLastError());
     return VG_OK;
 }
 
-vg_status launch_lm_init(vg_batch* b, double* d_state, double lambda0) {
-    k_lm_init<<<(int)((b->F + 63) / 64), 64, 0, b->ctx->stream>>>(b->F, d_state, lambda0);
+vg_status launch_fill(vg_context* ctx, double* d_ptr, int64_t n, double v) {
+    if (n <= 0) return VG_OK;
+    k_fill<<<(int)((n + 255) / 256), 256, 0, ctx->stream>>>(d_ptr, n, v);
     VG_HIP(hipGetLastError());
     return VG_OK;
 }

@@ -321,6 +321,27 @@ class FactorBatch:
         check(load().vg_lm_run(self.handle, _p(P), iters, float(lambda0), _p(out), _p(acc), _p(eh)))
         return pose4x4(out), acc.astype(bool), eh
 
+    def lm_step_async(self, d_poses: torch.Tensor, d_lambda: torch.Tensor, want_e=True, want_accepted=True):
+        """One device LM iteration in place on (F x 12) poses and (F) lambda (FP64 tensors);
+        returns (e at the input poses, accepted flags) as device tensors (or None)."""
+        assert d_poses.dtype == torch.float64 and d_poses.is_contiguous() and d_poses.shape == (self.F, 12)
+        assert d_lambda.dtype == torch.float64 and d_lambda.is_contiguous() and d_lambda.shape == (self.F,)
+        e = torch.empty(self.F, dtype=torch.float64, device=d_poses.device) if want_e else None
+        acc = torch.empty(self.F, dtype=torch.int32, device=d_poses.device) if want_accepted else None
+        self.ctx.enter()
+        check(load().vg_lm_step_async(self.handle, _tp(d_poses), _tp(d_lambda), _tp(e), _tp(acc)))
+        self.ctx.leave()
+        return e, acc
+
+    def work(self):
+        """Work of the last linearize / evaluate / overlap: (walked points F, walked chunks F,
+        table lookups F x L)."""
+        wp = np.zeros(self.F, dtype=np.int64)
+        wc = np.zeros(self.F, dtype=np.int64)
+        lk = np.zeros((self.F, self.L), dtype=np.int64)
+        check(load().vg_batch_work(self.handle, _p(wp), _p(wc), _p(lk)))
+        return wp, wc, lk
+
     def correspondences(self, pose, factor):
         P = poses12(pose)[0]
         n = self.sources[factor].n

@@ -80,3 +80,33 @@ def test_precision_stress_10km(vg):
             x.close()
     assert res["fp64"][0] < 1e-9 and res["fp64"][1] < 1e-8
     assert res["fp32c"][0] < 1e-5 and res["fp32c"][1] < 1e-4
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32c", 1e-5)])
+def test_lm_step_async_matches_oracle(vg, lm_case, prec, tol):
+    """Ten stream-ordered LM steps on device pointers (poses and lambda stay on the
+    device between steps) reproduce the oracle's accept sequence, error history
+    and final pose."""
+    import torch
+    vgicp, ctx = vg
+    cfg, ref = lm_case
+    maps, srcs, batch = vgicp.build_workload(ctx, cfg, precision=prec)
+    d_T = torch.tensor(vgicp.poses12([cfg["poses"][0]]), device="cuda")
+    lam = torch.full((1,), 1e-4, dtype=torch.float64, device="cuda")
+    es, accs = [], []
+    for _ in range(10):
+        e, acc = batch.lm_step_async(d_T, lam)
+        es.append(e)
+        accs.append(acc)
+    torch.cuda.synchronize()
+    acc = np.array([int(a.item()) for a in accs])
+    eh = np.array([float(x.item()) for x in es])
+    T = vgicp.pose4x4(d_T.cpu().numpy())[0]
+    rot, tr = pose_error(ref["pose"], T)
+    print(prec, "step accepted", acc.tolist(), "oracle", ref["accepted"].astype(int).tolist(),
+          "pose diff rad %.3g m %.3g" % (rot, tr), "lambda %.3g" % lam.item(), flush=True)
+    assert acc.tolist() == ref["accepted"].astype(int).tolist()
+    assert rot < tol and tr < tol
+    np.testing.assert_allclose(eh, ref["e"], rtol=1e-5)
+    assert lam.item() == pytest.approx(ref["lambda"], rel=1e-12)
+    batch.close()

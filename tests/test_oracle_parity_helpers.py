@@ -174,3 +174,59 @@ def test_face_trace_is_the_distance_to_the_nearest_face():
                     out[a] += s * (f * (1 + 1e-6) + 1e-12)
                     changed.append(not np.array_equal(np.floor(out / r).astype(np.int64), key))
             assert any(changed), (k, l, f)
+
+
+def test_block_errors_see_what_whole_matrix_norms_hide():
+    """A per-mille error in the translation block of H (or of b) is invisible in
+    the whole-matrix relative error, which the rotation block dominates, but not
+    in the block errors; an exact copy has every block error 0."""
+    from oracle.parity import block_errors, rel_err
+    cfg = synth.config1(seed=3, n_target=4000, n_source=1500)
+    of = oracle.factor_from_clouds(cfg["sources"][0], cfg["targets"][0], cfg["resolutions"])
+    r = of.linearize(cfg["poses"][0])
+    H, b = r["H"], r["b"]
+    assert max(block_errors(H, b, H, b).values()) == 0.0
+    Hp = H.copy()
+    Hp[3:, 3:] *= 1.0 + 2e-3
+    errs = block_errors(Hp, b, H, b)
+    assert errs["H_vv"] == pytest.approx(2e-3, rel=1e-6)
+    assert errs["H_scaled"] >= 2e-3 * (1 - 1e-9)
+    assert errs["H_ww"] == 0.0 and errs["H_wv"] == 0.0
+    assert rel_err(Hp, H) < errs["H_vv"] / 10          # the whole-matrix norm hides most of it
+    bp = b.copy()
+    bp[3:] *= 1.0 + 2e-3
+    sc = of.gradient_scale(cfg["poses"][0])
+    errs = block_errors(H, bp, H, b, sc)
+    assert errs["b_v_own"] == pytest.approx(2e-3, rel=1e-6) and errs["b_w_own"] == 0.0
+    assert errs["b_v"] == pytest.approx(2e-3 * np.linalg.norm(b[3:]) / sc[1], rel=1e-6) and errs["b_w"] == 0.0
+    # an off-diagonal entry is measured against the geometric mean of its diagonal entries
+    Hq = H.copy()
+    Hq[0, 5] += 1e-4 * np.sqrt(H[0, 0] * H[5, 5])
+    assert block_errors(Hq, b, H, b)["H_scaled"] == pytest.approx(1e-4, rel=1e-9)
+
+
+def test_gradient_scale_is_the_sum_of_per_point_norms():
+    """gradient_scale = sum over matched (point, level) pairs of the norms of the
+    two halves of each pair's b, summed here from the per-point terms (which are
+    pinned to add up to the factor's b); it bounds |b| of each half."""
+    cfg = synth.config1(seed=8, n_target=3000, n_source=300, resolutions=(0.5, 1.0))
+    of = oracle.factor_from_clouds(cfg["sources"][0], cfg["targets"][0], cfg["resolutions"])
+    pose = cfg["poses_true"][0]
+    tr = of.linearize(pose, trace=True)
+    sw = sv = 0.0
+    bsum = np.zeros(6)
+    for k in range(of.n):
+        for l in range(2):
+            if tr["vidx"][k, l] < 0:
+                continue
+            ok, _, _, bk = of.point_terms(pose, k, l, tr["keys"][k, l])
+            assert ok
+            sw += np.linalg.norm(bk[:3])
+            sv += np.linalg.norm(bk[3:])
+            bsum += bk
+    gw, gv = of.gradient_scale(pose)
+    assert gw == pytest.approx(sw, rel=1e-12) and gv == pytest.approx(sv, rel=1e-12)
+    np.testing.assert_allclose(bsum, tr["b"], rtol=1e-9, atol=1e-9 * np.abs(tr["b"]).max())
+    assert np.linalg.norm(tr["b"][:3]) <= gw and np.linalg.norm(tr["b"][3:]) <= gv
+    # at the true pose the translation half cancels: |b_v| is a small part of its scale
+    print("cancellation |b_v| / scale = %.3g" % (np.linalg.norm(tr["b"][3:]) / gv))

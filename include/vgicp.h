@@ -246,6 +246,19 @@ vg_status vg_overlap(vg_batch* batch, const double* poses, double* overlap);
 vg_status vg_linearize_async(vg_batch* batch, const double* d_poses, double* d_out, int64_t* d_inliers);
 vg_status vg_evaluate_async(vg_batch* batch, const double* d_poses, double* d_e);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as vg_linearize_async, bit for bit, with no
+ * allocation, free or allocating library call.  The kernels' scratch (tile
+ * counters, staged FP32 poses, one partial row of 40 doubles per tile) lives in
+ * a fixed 32 MiB device array, one per device, held until the process ends; a
+ * batch needing more (roughly 256 B + 64 B per factor + 320 B per tile, i.e.
+ * about 100,000 tiles) fails with VG_ERR_CAPACITY.  Every call on a device
+ * shares that device's array, so calls that overlap in time on one device (two
+ * streams, two threads) race and must be serialized by the caller.  The work
+ * counts of vg_batch_work are not updated by this call. */
+vg_status vg_linearize_noalloc(vg_batch* batch, const double* d_poses, double* d_out, int64_t* d_inliers);
+
 /* Exact gradient of e (Eq. (em), Eq. (d2d); W recomputed, not frozen;
  * correspondences held at the given poses), scaled by d_grad_e (F).  d_jr: F x 36 FP64 right Jacobians
  * J_r(xi) to apply (grad_xi = J_r^T de/dxi') or NULL for the plain tangent

@@ -84,6 +84,7 @@ SIGNATURES = {
     "vg_evaluate": (C.c_int, [P, P, P]),
     "vg_overlap": (C.c_int, [P, P, P]),
     "vg_linearize_async": (C.c_int, [P, P, P, P]),
+    "vg_linearize_noalloc": (C.c_int, [P, P, P, P]),
     "vg_evaluate_async": (C.c_int, [P, P, P]),
     "vg_backward_async": (C.c_int, [P, P, P, P, P, P, I32]),
     "vg_se3_retract_async": (C.c_int, [P, I64, P, P, P, P]),

@@ -9,9 +9,17 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 
 #include "vg_internal.h"
+
+// Device scratch of the allocation-free linearization (vg_linearize_noalloc):
+// tile counters, staged FP32 poses and tile partial rows.  Every device the
+// library runs on holds its own copy until the process ends; host code reaches
+// it only through the per-device address taken with hipGetSymbolAddress.
+static constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -28,6 +36,14 @@ constexpr uint32_t kBatMagic = 0xBA7C0001u;
 constexpr double kMaxCompensatedExtent = 500.0;
 
 thread_local std::string g_err;
+
+// Device address of `scratch` on each device, taken once per device when the
+// first context on it is created.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[kMaxDevices] = {};
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
 
 bool finite_all(const double* p, int64_t n) {
     for (int64_t i = 0; i < n; ++i)
@@ -171,6 +187,20 @@ extern "C" vg_status vg_context_create(int32_t device, void* hip_stream, vg_cont
     auto* c = new vg_context();
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
+    if (device < kMaxDevices) {
+        // this device's copy of the fixed scratch (device current); a failure only
+        // disables vg_linearize_noalloc, which reports it
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_done[device]) {
+            void* ptr = nullptr;
+            const hipError_t se = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (se != hipSuccess) (void)hipGetLastError();
+            g_scratch_err[device] = se;
+            g_scratch_ptr[device] = se == hipSuccess ? ptr : nullptr;
+            g_scratch_done[device] = true;
+        }
+        c->scratch = g_scratch_ptr[device];
+    }
     c->arch = arch;
     c->name = prop.name;
     if (hip_stream != nullptr) {
@@ -1075,6 +1105,39 @@ extern "C" vg_status vg_linearize_async(vg_batch* b, const double* d_poses, doub
     if (d_poses == nullptr || d_out == nullptr) return invalid("d_poses or d_out is NULL");
     VG_HIP(hipSetDevice(b->ctx->device));
     return run_linearize_device(b, d_poses, d_out, d_inliers);
+}
+
+extern "C" vg_status vg_linearize_noalloc(vg_batch* b, const double* d_poses, double* d_out, int64_t* d_inliers) {
+    g_err.clear();
+    if (!bat_ok(b)) return state_err("invalid batch");
+    if (d_poses == nullptr || d_out == nullptr) return invalid("d_poses or d_out is NULL");
+    VG_HIP(hipSetDevice(b->ctx->device));
+    if (b->ctx->scratch == nullptr) {
+        const int dev = b->ctx->device;
+        set_error(std::string("no fixed scratch on this device: ") +
+                  (dev < kMaxDevices ? hipGetErrorString(g_scratch_err[dev]) : "device index beyond the table"));
+        return VG_ERR_HIP;
+    }
+    // layout: counters (256 B), staged poses (F x 16 floats), tile rows (tiles x kRow doubles)
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t n_tiles = b->h_tiles.size();
+    const size_t off_posef = 256;
+    const size_t off_rows = off_posef + up(sizeof(float) * 16 * (size_t)b->F);
+    const size_t need = off_rows + up(sizeof(double) * kRow * n_tiles);
+    if (need > kScratchBytes) {
+        char msg[256];
+        std::snprintf(msg, sizeof msg,
+                      "batch needs %zu bytes of scratch (%lld factors, %zu tiles); the fixed scratch holds %zu",
+                      need, (long long)b->F, n_tiles, kScratchBytes);
+        set_error(msg);
+        return VG_ERR_CAPACITY;
+    }
+    unsigned char* base = static_cast<unsigned char*>(b->ctx->scratch);
+    const Workspace ws{reinterpret_cast<double*>(base + off_rows), reinterpret_cast<uint32_t*>(base),
+                       reinterpret_cast<float*>(base + off_posef), nullptr};
+    // the tile counters must start at zero; another call may have left them anywhere
+    VG_TRY(launch_zero(b->ctx, ws.counter, sizeof(uint32_t) * kParts));
+    return run_linearize_device(b, ws, d_poses, d_out, d_inliers);
 }
 
 extern "C" vg_status vg_evaluate_async(vg_batch* b, const double* d_poses, double* d_e) {

@@ -289,6 +289,18 @@ class FactorBatch:
         self.ctx.leave()
         return out, inl
 
+    def linearize_noalloc(self, d_poses: torch.Tensor, out: torch.Tensor, inliers: torch.Tensor = None):
+        """vg_linearize_async's results into caller-provided device tensors (F x 43 FP64,
+        F x L int64 or None), with the kernels' scratch in the library's fixed array."""
+        d_poses = d_poses.contiguous()
+        assert out.is_contiguous() and out.dtype == torch.float64 and out.shape == (self.F, 43)
+        assert inliers is None or (inliers.is_contiguous() and inliers.dtype == torch.int64
+                                   and inliers.shape == (self.F, self.L))
+        self.ctx.enter()
+        check(load().vg_linearize_noalloc(self.handle, _tp(d_poses), _tp(out), _tp(inliers)))
+        self.ctx.leave()
+        return out, inliers
+
     def evaluate_async(self, d_poses: torch.Tensor):
         d_poses = d_poses.contiguous()
         e = torch.empty(self.F, dtype=torch.float64, device=d_poses.device)

@@ -322,7 +322,10 @@ vg_status vg_batch_work(vg_batch* batch, int64_t* walked_points, int64_t* walked
  * tune_cache path, appended to that file under a key made of the device name
  * and the batch signature (precision, F, total points, levels, validation).
  * chosen (may be NULL) receives {block_threads, tile_points, blocks_per_cu,
- * tile_order}.  Both tile orders are candidates. */
+ * tile_order}.  Both tile orders are candidates.  A batch created with
+ * plain_per_factor is tuned for its own loop instead: tile points x block
+ * threads candidates, each timed over whole calls of that loop (so a single
+ * factor's launch can fill the device with small tiles). */
 vg_status vg_batch_tune(vg_batch* batch, const double* poses, int32_t reps, int32_t* chosen);
 
 /* ---- pose graphs: two-node expansion and normal-equation assembly ------- */

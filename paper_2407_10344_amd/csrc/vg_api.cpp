@@ -1389,6 +1389,45 @@ extern "C" vg_status vg_batch_tune(vg_batch* b, const double* poses, int32_t rep
     hipStream_t st = b->ctx->stream;
     std::memcpy(b->h_poses, poses, sizeof(double) * 12 * b->F);
     VG_HIP(hipMemcpyAsync(b->d_poses, b->h_poses, sizeof(double) * 12 * b->F, hipMemcpyHostToDevice, st));
+    if (b->opt.plain_per_factor) {
+        // the per-factor loop: every factor is its own launch, so its tiles must
+        // be small enough to fill the device on their own; each candidate is
+        // timed on the whole loop (uploads, launches, downloads, synchronizations)
+        const int ptiles[] = {8192, 2048, 1024, 512, 256};
+        const int pblocks[] = {256, 128};
+        float best = 1e30f;
+        int bb = b->block, bt = b->tile_points;
+        for (int tp : ptiles)
+            for (int bl : pblocks) {
+                b->tile_points = tp;
+                b->block = bl;
+                b->blocks_per_cu = default_blocks_per_cu(bl);
+                build_tiles(b);
+                VG_TRY(upload_schedule(b));
+                VG_TRY(linearize_host(b));   // warm-up
+                const auto t0 = std::chrono::steady_clock::now();
+                for (int r = 0; r < reps; ++r) VG_TRY(linearize_host(b));
+                const float ms = (float)(std::chrono::duration<double, std::milli>(
+                                             std::chrono::steady_clock::now() - t0).count() / reps);
+                if (ms < best * 0.985f) {
+                    best = ms;
+                    bb = bl;
+                    bt = tp;
+                }
+            }
+        b->block = bb;
+        b->tile_points = bt;
+        b->blocks_per_cu = default_blocks_per_cu(bb);
+        build_tiles(b);
+        VG_TRY(upload_schedule(b));
+        if (chosen) {
+            chosen[0] = bb;
+            chosen[1] = bt;
+            chosen[2] = b->blocks_per_cu;
+            chosen[3] = b->tile_order;
+        }
+        return VG_OK;
+    }
     // candidates in order of preference: a later candidate replaces an earlier one
     // only when it is faster by more than 1.5 %, so timing noise does not flip the choice
     const int orders[] = {1, 2};

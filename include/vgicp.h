@@ -26,7 +26,7 @@
  *     two, and every resolution is itself a power of two (so y / r is exact).
  *   - Voxel keys are limited to |q - q_origin| < 8192 per axis around the map
  *     origin (the first point snapped to the coarsest voxel), and a level holds
- *     fewer than 268,435,454 voxels.
+ *     fewer than 67,108,864 voxels.
  *
  * Error behaviour: every call returns a vg_status (0 = VG_OK).  No exception
  * crosses the ABI.  On failure vg_last_error() returns a message that stays
@@ -153,7 +153,8 @@ vg_status vg_voxelmap_destroy(vg_voxelmap* map);
  * stores them relative to per-64-point anchors, with a ball and a box that
  * bound each 64-point chunk (chunks that cannot reach a target's voxels are
  * skipped by the kernels); every per-point output of the library is reported
- * in the caller's order.  Covariances must be SPD (VG_ERR_NOT_SPD otherwise). */
+ * in the caller's order.  Covariances must be SPD (VG_ERR_NOT_SPD otherwise).
+ * n < 2^27 (the kernels address a source's arrays with 32-bit offsets). */
 vg_status vg_create_source(vg_context* ctx, const double* xyz, const double* cov, const double* normals,
                            int64_t n, vg_source** out);
 /* Replace the source positions from a device buffer in caller order (n x 3,

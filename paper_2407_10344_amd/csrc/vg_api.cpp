@@ -419,7 +419,7 @@ extern "C" vg_status vg_create_source(vg_context* ctx, const double* xyz, const 
     if (out == nullptr) return invalid("out is NULL");
     *out = nullptr;
     if (n < 0) return invalid("n < 0");
-    if (n >= (int64_t)1 << 31) return invalid("n must be below 2^31");
+    if (n >= (int64_t)1 << 27) return invalid("n must be below 2^27 (134,217,728 points per source)");
     if (n > 0 && (xyz == nullptr || cov == nullptr)) return invalid("xyz or cov is NULL");
     if (n > 0 && !finite_all(xyz, 3 * n)) return invalid("xyz has non-finite values");
     if (n > 0 && !finite_all(cov, 6 * n)) return invalid("cov has non-finite values");
@@ -563,6 +563,7 @@ extern "C" vg_status vg_create_source_from_cloud(vg_context* ctx, const vg_cloud
     if (out == nullptr) return invalid("out is NULL");
     *out = nullptr;
     VG_HIP(hipSetDevice(ctx->device));
+    if (cloud->m >= (int64_t)1 << 27) return invalid("a source holds fewer than 2^27 points");
     return make_source(ctx, cloud->xyz, cloud->cov, cloud->nrm, true, cloud->m, cloud->first, out);
 }
 

@@ -65,31 +65,58 @@ __host__ __device__ __forceinline__ uint64_t block_key(uint64_t ux, uint64_t uy,
     return ((ux >> kBlockShift) << (2 * kBlockBits)) | ((uy >> kBlockShift) << kBlockBits) | (uz >> kBlockShift);
 }
 
+// Load of a T at a 32-bit byte offset from a base pointer.  With a uniform
+// base this compiles to a global load with the base in scalar registers and
+// only the 32-bit offset in a vector register (no 64-bit address arithmetic
+// per lane).
+template <typename T>
+__device__ __forceinline__ T load_off(const void* base, uint32_t byte_off) {
+    return *gbl(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint64_t)byte_off));
+}
+
 // Record index of relative key (kx, ky, kz) (each in [-8192, 8191]), or -1.
-// 32-bit arithmetic except the 36-bit block key; the occupancy test and the
-// popcount below the voxel's bit take no branch on which half holds the bit.
+// The first table entry decides almost every lookup (load factor <= 1/4): it
+// is either the block, or empty, or (rarely) another block, and only then is
+// the chain walked.  The occupancy test and the popcount below the voxel's bit
+// take no branch on which half of the mask holds the bit.
 __device__ __forceinline__ int32_t lookup(const uint64_t* __restrict__ slots, uint32_t log2cap, int32_t kx,
                                           int32_t ky, int32_t kz) {
     const uint32_t ux = (uint32_t)(kx + kKeyBias), uy = (uint32_t)(ky + kKeyBias), uz = (uint32_t)(kz + kKeyBias);
     const uint32_t bx = ux >> kBlockShift, by = uy >> kBlockShift, bz = uz >> kBlockShift;
     const uint64_t bk = ((uint64_t)bx << (2 * kBlockBits)) | (uint64_t)((by << kBlockBits) | bz);
-    const uint32_t local = (ux & 3u) | ((uy & 3u) << 2) | ((uz & 3u) << 4);
-    const bool upper = local >= 32u;
-    const uint32_t below_mask = (1u << (local & 31u)) - 1u;
-    const uint32_t mask = (1u << log2cap) - 1u;
     uint32_t h = slot_of_block(bx, by, bz, log2cap);
-    for (uint32_t it = 0; it <= mask; ++it) {
-        const u64x2 e = *gbl(reinterpret_cast<const u64x2*>(slots + 2 * (uint64_t)h));
-        if (e.x == kEmpty) return -1;
-        if ((e.x >> kBaseBits) == bk) {
-            const uint32_t lo = (uint32_t)e.y, hi = (uint32_t)(e.y >> 32);
-            if (!(((upper ? hi : lo) >> (local & 31u)) & 1u)) return -1;
-            const uint32_t below = __popc(upper ? lo : (lo & below_mask)) + __popc(upper ? (hi & below_mask) : 0u);
-            return (int32_t)(e.x & kBaseMask) + (int32_t)below;
+    u64x2 e = load_off<u64x2>(slots, h << 4);
+    bool same = (e.x >> kBaseBits) == bk;
+    if (!same && e.x != kEmpty) {
+        // another block in the first slot: walk the chain (linear probing)
+        const uint32_t mask = (1u << log2cap) - 1u;
+        for (uint32_t it = 0; it < mask; ++it) {
+            h = (h + 1u) & mask;
+            e = load_off<u64x2>(slots, h << 4);
+            same = (e.x >> kBaseBits) == bk;
+            if (same || e.x == kEmpty) break;
         }
-        h = (h + 1u) & mask;
     }
-    return -1;
+    // an empty entry never holds the block (a valid entry word is never all ones)
+    const uint32_t local = (ux & 3u) | ((uy & 3u) << 2) | ((uz & 3u) << 4);
+    const bool upper = (uz & 2u) != 0u;   // bit 32..63 of the mask
+    const uint32_t sh = local & 31u;
+    const uint32_t lo = (uint32_t)e.y, hi = (uint32_t)(e.y >> 32);
+    const bool occupied = (((upper ? hi : lo) >> sh) & 1u) != 0u;
+    const uint32_t below_mask = (1u << sh) - 1u;
+    const uint32_t below = __popc(lo & (upper ? ~0u : below_mask)) + __popc(hi & (upper ? below_mask : 0u));
+    const int32_t rec = (int32_t)((uint32_t)e.x & (uint32_t)kBaseMask) + (int32_t)below;
+    return (same && e.x != kEmpty && occupied) ? rec : -1;
+}
+
+// Buffer resource over `bytes` bytes at p (raw buffer, no swizzle): loads
+// through it take a scalar base plus a 32-bit offset and return 0 beyond the
+// end instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float rsrc_load_f32(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
 }
 
 // 1/x without the correctly rounded division sequence: hardware reciprocal

@@ -183,21 +183,22 @@ struct RawPoint<kF64> {
     double x[3];
 };
 
+// Point `base + lane` of a source (internal order); base is the chunk's first
+// point (uniform), so the addresses are a scalar base plus the lane's offset.
+// Pad points (up to n_pad) are stored as zeros, so every lane may load.
 template <int PREC>
-__device__ __forceinline__ void load_point(const FactorDesc* __restrict__ Fp, int64_t i, int64_t n_pad,
-                                           RawPoint<PREC>& p) {
+__device__ __forceinline__ void load_point(const FactorDesc* __restrict__ Fp, __amdgpu_buffer_rsrc_t xr,
+                                           uint32_t base, int64_t n_pad, uint32_t lane, RawPoint<PREC>& p) {
     if constexpr (PREC == kC32) {
-        const auto X = gbl(Fp->dxyz);
+        // buffer loads: the component's and chunk's offset is a scalar, the lane's a constant
 #pragma unroll
-        for (int a = 0; a < 3; ++a) p.x[a] = X[a * n_pad + i];
+        for (int a = 0; a < 3; ++a) p.x[a] = rsrc_load_f32(xr, lane * 4u, (uint32_t)(a * n_pad + base) * 4u);
     } else if constexpr (PREC == kN32) {
-        const auto X = gbl(Fp->axyz);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) p.x[a] = X[a * n_pad + i];
+        for (int a = 0; a < 3; ++a) p.x[a] = load_off<float>(Fp->axyz + a * n_pad + base, lane * 4u);
     } else {
-        const auto X = gbl(Fp->xyz64);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) p.x[a] = X[a * n_pad + i];
+        for (int a = 0; a < 3; ++a) p.x[a] = load_off<double>(Fp->xyz64 + a * n_pad + base, lane * 8u);
     }
 }
 
@@ -207,10 +208,11 @@ template <int PREC, typename TS, typename T>
 __device__ __forceinline__ void point_S(const FactorDesc* __restrict__ Fp, int64_t i, int64_t n_pad,
                                         const double* P, const T* R, TS* S) {
     if constexpr (PREC == kC32) {
-        const auto Cv = gbl(Fp->cov);
+        // the covariances as a buffer (6 x n_pad floats): one lane offset, scalar component offsets
+        const __amdgpu_buffer_rsrc_t cr = raw_rsrc(Fp->cov, (uint32_t)(6 * n_pad * (int64_t)sizeof(float)));
         double R64[9], C64[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) C64[k] = (double)Cv[k * n_pad + i];
+        for (int k = 0; k < 6; ++k) C64[k] = (double)rsrc_load_f32(cr, (uint32_t)i * 4u, (uint32_t)(k * n_pad) * 4u);
 #pragma unroll
         for (int k = 0; k < 9; ++k) R64[k] = P[k];
         rotate_cov(R64, C64, S);
@@ -247,10 +249,10 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
         inv_r = lv.inv_r;
         r64 = lv.r64;
     }
-    const float* rec = rec_base + (int64_t)v * kRec32;
-    const f32x4 q0 = *gbl(reinterpret_cast<const f32x4*>(rec));
-    const auto c2 = gbl(reinterpret_cast<const f64x2*>(rec + 4));
-    const f64x2 cva = c2[0], cvb = c2[1], cvc = c2[2];
+    const uint32_t ro = (uint32_t)v * (uint32_t)(kRec32 * sizeof(float));
+    const f32x4 q0 = load_off<f32x4>(rec_base, ro);
+    const f64x2 cva = load_off<f64x2>(rec_base, ro + 16u), cvb = load_off<f64x2>(rec_base, ro + 32u),
+                cvc = load_off<f64x2>(rec_base, ro + 48u);
     double S[6];
     point_S<kC32>(Fp, (int64_t)i, n_pad, P, R, S);
     int32_t jk[3];
@@ -611,25 +613,29 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
         const ProbeLevel pl0(Fp->lv[0]);
         // each wave walks list entries wave, wave + NW, ...; the next chunk's point
         // is loaded before the current one is processed, so its latency overlaps
+        // the source's positions as a buffer (3 x n_pad floats; sources hold fewer than 2^27 points)
+        const __amdgpu_buffer_rsrc_t xr = raw_rsrc(Fp->dxyz, (uint32_t)(3 * n_pad * (int64_t)sizeof(float)));
+        const int32_t n32 = (int32_t)n;
         RawPoint<PREC> nxt;
         if (wave < nlive) {
             const int c0 = __builtin_amdgcn_readfirstlane(sh.live[wave]);
-            const int64_t i0 = (int64_t)(tile.chunk0 + c0) * kChunk + lane;
-            if (i0 < n) load_point<PREC>(Fp, i0, n_pad, nxt);
+            load_point<PREC>(Fp, xr, (uint32_t)(tile.chunk0 + c0) * kChunk, n_pad, (uint32_t)lane, nxt);
         }
         for (int j = wave; j < nlive; j += NW) {
             const int c = __builtin_amdgcn_readfirstlane(sh.live[j]);
-            const int64_t i = (int64_t)(tile.chunk0 + c) * kChunk + lane;
+            // point index (sources hold fewer than 2^31 points) and the chunk's
+            // point count (uniform: only a source's last chunk is partial)
+            const uint32_t base = (uint32_t)(tile.chunk0 + c) * kChunk;
+            const int32_t i = (int32_t)(base + (uint32_t)lane);
+            const bool live = lane < min(kChunk, n32 - (int32_t)base);
             const RawPoint<PREC> cur = nxt;
             if (j + NW < nlive) {
                 const int cn = __builtin_amdgcn_readfirstlane(sh.live[j + NW]);
-                const int64_t in = (int64_t)(tile.chunk0 + cn) * kChunk + lane;
-                if (in < n) load_point<PREC>(Fp, in, n_pad, nxt);
+                load_point<PREC>(Fp, xr, (uint32_t)(tile.chunk0 + cn) * kChunk, n_pad, (uint32_t)lane, nxt);
             }
             if constexpr (CMP && PREC == kF64) {
                 // ---- FP64 mode: probe every point, queue its hits, drain full waves
                 HitQueue& Q = s_q[wave];
-                const bool live = i < n;
                 const double x0 = cur.x[0], x1 = cur.x[1], x2 = cur.x[2];
                 double yl[3];
 #pragma unroll
@@ -679,7 +685,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
             } else if constexpr (CMP) {
                 // ---- probe every point, queue its hits, drain full waves of hits
                 HitQueue& Q = s_q[wave];
-                const bool live = i < n;
                 const float dx = cur.x[0], dy = cur.x[1], dz = cur.x[2];
                 float yl[3];
 #pragma unroll
@@ -734,7 +739,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 }
                 continue;
             }
-            if (i >= n) continue;
+            if (!live) continue;
             // ---- load the point, transform it
             // yl: transformed position (kC32: relative to the anchor's coarse voxel corner)
             T x[3], z[3];

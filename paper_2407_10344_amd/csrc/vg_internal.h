@@ -21,7 +21,9 @@ constexpr int kBlockShift = 2;          // voxel blocks of 4 x 4 x 4
 constexpr int kBlockBits = kKeyBits - kBlockShift;   // 12 bits per axis of a block key
 constexpr int kBaseBits = 28;           // first-record index bits of a block entry
 constexpr uint64_t kBaseMask = (1ull << kBaseBits) - 1;
-constexpr int64_t kMaxVoxels = (int64_t)kBaseMask - 1;  // so a valid entry word is never all ones
+// voxels per level: records are addressed by 32-bit byte offsets (64 B each), so
+// fewer than 2^26; this also keeps a valid entry word from ever being all ones
+constexpr int64_t kMaxVoxels = ((int64_t)1 << 26) - 1;
 constexpr uint64_t kEmpty = ~0ull;      // empty block-table entry
 constexpr int kTerms = 28;              // e, 21 upper-triangular H, 6 b
 // partial row of a tile (FP64): 28 terms, inliers per level, then the work the

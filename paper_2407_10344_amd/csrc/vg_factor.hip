@@ -85,6 +85,56 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// a + b after exchanging the upper half of a's lanes with the lower half of
+// b's (stride 32: v_permlane32_swap; stride 16: v_permlane16_swap, which
+// exchanges the odd 16-lane rows of a with the even rows of b).  Lanes whose
+// stride bit is clear get a (own) + a (partner's), the others b (partner's) +
+// b (own): one butterfly step of a wave sum that halves the values per lane.
+template <int STRIDE>
+__device__ __forceinline__ double swap_add(double a, double b) {
+    const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+    const uint32_t alo = (uint32_t)ua, ahi = (uint32_t)(ua >> 32), blo = (uint32_t)ub, bhi = (uint32_t)(ub >> 32);
+    uint32_t x0, x1, y0, y1;
+    if constexpr (STRIDE == 32) {
+        const auto lo = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+        x0 = lo[0]; y0 = lo[1]; x1 = hi[0]; y1 = hi[1];
+    } else {
+        const auto lo = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+        x0 = lo[0]; y0 = lo[1]; x1 = hi[0]; y1 = hi[1];
+    }
+    return __longlong_as_double((int64_t)(((uint64_t)x1 << 32) | x0)) +
+           __longlong_as_double((int64_t)(((uint64_t)y1 << 32) | y0));
+}
+
+// Wave sum of 32 FP64 values per lane, transposed: each butterfly step keeps
+// half of the values on each lane (the half selected by the lane's stride
+// bit), so after five steps lanes 2k and 2k + 1 hold partial sums of value k
+// over complementary halves of the wave, and the last step adds them.  Returns
+// the sum of value lane / 2.  The order of the additions is fixed.
+template <int O, int CNT>
+__device__ __forceinline__ void xor_step(double (&v)[32], int lane) {
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int k = 0; k < CNT; ++k) {
+        const double send = up ? v[k] : v[k + CNT];
+        const double keep = up ? v[k + CNT] : v[k];
+        v[k] = keep + __shfl_xor(send, O, 64);
+    }
+}
+
+__device__ __forceinline__ double wave_sum_transposed(double (&v)[32], int lane) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = swap_add<32>(v[k], v[k + 16]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = swap_add<16>(v[k], v[k + 8]);
+    xor_step<8, 4>(v, lane);
+    xor_step<4, 2>(v, lane);
+    xor_step<2, 1>(v, lane);
+    return v[0] + __shfl_xor(v[0], 1, 64);
+}
+
 // Gauss-Newton terms of one (point, voxel) pair in the target orientation.
 template <typename T, typename A>
 __device__ __forceinline__ void add_lin_terms(A& acc, const T d[3], const T w[6], const T z[3]) {
@@ -438,13 +488,16 @@ __global__ void k_stage_poses(int64_t F, const double* __restrict__ poses, float
     posef[i] = (k < 12) ? (float)poses[12 * f + k] : 0.0f;
 }
 
-template <int MODE, int PREC, int BLOCK, bool KH>
+// VAL: surface validation (a compile-time switch, so that batches without it
+// carry none of its state through the point loop)
+template <int MODE, int PREC, int BLOCK, bool KH, bool VAL>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per_eu<PREC, KH>()))) void k_tiles(
     const FactorDesc* __restrict__ fac, const Tile* __restrict__ tiles, int32_t t_begin, int32_t t_end,
     const double* __restrict__ poses, const float* __restrict__ posef, double* __restrict__ partials,
-    uint32_t* __restrict__ counter, int32_t validate, const double* __restrict__ grad_e,
+    uint32_t* __restrict__ counter, const double* __restrict__ grad_e,
     void* __restrict__ grad_points, void* __restrict__ grad_slab, int32_t points_dtype, int32_t interleave) {
     using T = typename PT<PREC>::T;
+    constexpr bool validate = VAL;
     constexpr int NW = BLOCK / 64;
     constexpr bool KAHAN = KH && (PREC == kC32);
     constexpr int NT = (MODE == kLin) ? kTerms : (MODE == kBwd ? 6 : 1);
@@ -947,14 +1000,23 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
         }
         // ---------------------------------------------------------------- reduction of the tile
         // lanes -> wave -> tile: FP64 except kN32, which stays FP32 end to end
+        if constexpr (PREC != kN32 && NT == kTerms) {
+            // the 28 terms in one transposed butterfly (value k ends on lanes 2k, 2k + 1)
+            double v[32];
 #pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            if constexpr (PREC == kN32) {
-                const float v = wave_sum(acc.get(k));
-                if (lane == 0) s_red[wave][k] = (double)v;
-            } else {
-                const double v = wave_sum(acc.get64(k));
-                if (lane == 0) s_red[wave][k] = v;
+            for (int k = 0; k < 32; ++k) v[k] = k < NT ? acc.get64(k) : 0.0;
+            const double w = wave_sum_transposed(v, lane);
+            if ((lane & 1) == 0 && (lane >> 1) < NT) s_red[wave][lane >> 1] = w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
+                if constexpr (PREC == kN32) {
+                    const float v = wave_sum(acc.get(k));
+                    if (lane == 0) s_red[wave][k] = (double)v;
+                } else {
+                    const double v = wave_sum(acc.get64(k));
+                    if (lane == 0) s_red[wave][k] = v;
+                }
             }
         }
         if constexpr (MODE != kBwd) {
@@ -1199,15 +1261,14 @@ __global__ void k_fill_zero(uint32_t* p, int64_t n_words) {
 
 // ---------------------------------------------------------------- host launchers
 
-template <int MODE, int PREC, bool KH>
-static vg_status launch_tiles_t(vg_batch* b, const Workspace& ws, const double* d_poses, int32_t t0, int32_t t1,
+template <int MODE, int PREC, bool KH, bool VAL>
+static vg_status launch_tiles_v(vg_batch* b, const Workspace& ws, const double* d_poses, int32_t t0, int32_t t1,
                                 int grid, const double* d_grad_e, void* d_grad_points, int points_dtype) {
     hipStream_t st = b->ctx->stream;
-    const int v = b->opt.surface_validation;
 #define VG_LAUNCH(BS)                                                                                         \
-    k_tiles<MODE, PREC, BS, KH><<<grid, BS, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, ws.posef,          \
-                                                     ws.partials, ws.counter, v, d_grad_e, d_grad_points,      \
-                                                     b->d_gslab, points_dtype, b->tile_order == 2 ? 1 : 0)
+    k_tiles<MODE, PREC, BS, KH, VAL><<<grid, BS, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, ws.posef,     \
+                                                          ws.partials, ws.counter, d_grad_e, d_grad_points,    \
+                                                          b->d_gslab, points_dtype, b->tile_order == 2 ? 1 : 0)
     switch (b->block) {
         case 64: VG_LAUNCH(64); break;
         case 128: VG_LAUNCH(128); break;
@@ -1217,6 +1278,16 @@ static vg_status launch_tiles_t(vg_batch* b, const Workspace& ws, const double* 
 #undef VG_LAUNCH
     VG_HIP(hipGetLastError());
     return VG_OK;
+}
+
+template <int MODE, int PREC, bool KH>
+static vg_status launch_tiles_t(vg_batch* b, const Workspace& ws, const double* d_poses, int32_t t0, int32_t t1,
+                                int grid, const double* d_grad_e, void* d_grad_points, int points_dtype) {
+    if (b->opt.surface_validation)
+        return launch_tiles_v<MODE, PREC, KH, true>(b, ws, d_poses, t0, t1, grid, d_grad_e, d_grad_points,
+                                                    points_dtype);
+    return launch_tiles_v<MODE, PREC, KH, false>(b, ws, d_poses, t0, t1, grid, d_grad_e, d_grad_points,
+                                                 points_dtype);
 }
 
 vg_status launch_tiles(vg_batch* b, const Workspace& ws, int mode, const double* d_poses, int32_t t0, int32_t t1,

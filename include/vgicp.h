@@ -99,7 +99,8 @@ typedef struct {
                                    synchronization per factor (the per-factor loop the
                                    batched mechanism replaces) */
     int32_t block_threads;      /* 64, 128, 256 or 512 threads per workgroup; 0 = default */
-    int32_t tile_points;        /* source points per work tile, a multiple of 64; 0 = default */
+    int32_t tile_points;        /* source points per work tile, a multiple of 64 up to 32768;
+                                   0 = default */
     int32_t blocks_per_cu;      /* persistent workgroups per compute unit; 0 = default */
     int32_t lane_kahan;         /* VG_FP32_COMPENSATED only: 1 = Kahan-compensated FP32 sums
                                    inside each lane (sums above a lane are FP64 either way) */

@@ -730,7 +730,7 @@ bool tune_lookup(const vg_batch* b, int* block, int* tile, int* bpc, int* order)
 
 bool valid_shape(int block, int tile, int bpc) {
     return (block == 64 || block == 128 || block == 256 || block == 512) && tile >= kChunk && tile % kChunk == 0 &&
-           tile / kChunk <= kMaxTileChunks && bpc >= 1 && bpc <= 64;
+           tile <= kMaxTilePoints && bpc >= 1 && bpc <= 64;
 }
 
 // The batch's own buffers for the tile kernel and reduction.
@@ -877,7 +877,7 @@ extern "C" vg_status vg_create_factor_batch(vg_context* ctx, int64_t F, vg_sourc
     int block = o.block_threads ? o.block_threads : 256;
     int tile = o.tile_points ? o.tile_points : 2048;
     int bpc = o.blocks_per_cu ? o.blocks_per_cu : default_blocks_per_cu(block);
-    if (!valid_shape(block, tile, bpc)) return invalid("invalid launch shape (block 64/128/256/512, tile a multiple of 64 up to 8192)");
+    if (!valid_shape(block, tile, bpc)) return invalid("invalid launch shape (block 64/128/256/512, tile a multiple of 64 up to 32768)");
     if (o.tile_order < 0 || o.tile_order > 2) return invalid("tile_order must be 0, 1 or 2");
     if (o.precision == kC32) {
         for (int64_t f = 0; f < F; ++f)
@@ -1432,7 +1432,7 @@ extern "C" vg_status vg_batch_tune(vg_batch* b, const double* poses, int32_t rep
     // candidates in order of preference: a later candidate replaces an earlier one
     // only when it is faster by more than 1.5 %, so timing noise does not flip the choice
     const int orders[] = {1, 2};
-    const int tiles[] = {8192, 4096, 2048, 1024, 512, 256};
+    const int tiles[] = {8192, 16384, 32768, 4096, 2048, 1024, 512, 256};
     const int blocks[] = {256, 128, 512};
     const int occ[] = {2, 1, 4};   // multiples of the full-occupancy workgroup count
     float best = 1e30f;

@@ -215,7 +215,7 @@ struct TileShared {
 // 64 are queued, so at most 127 are ever held.  The FP64 mode leaves x, y, z
 // unused (its drain re-reads the FP64 position).
 constexpr int kQueue = 128;
-static_assert(kMaxTileChunks * kChunk < 65536, "per-tile counts are packed in 16 bits");
+static_assert(kMaxTilePoints < 65536, "per-tile counts are packed in 16 bits");
 struct HitQueue {
     float x[kQueue], y[kQueue], z[kQueue];   // point offset from its chunk anchor (compensated mode)
     int32_t pt[kQueue];                      // point index in the source (internal order)
@@ -587,76 +587,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
 #pragma unroll
             for (int i = 0; i < 3; ++i) cs[i] = P[i] * dc0 + P[3 + i] * dc1 + P[6 + i] * dc2;
         }
-        // ---------------------------------------------------------------- prologue: chunk anchors (kC32)
-        if constexpr (PREC == kC32) {
-            const LevelDesc& top = Fp->lv[L - 1];
-            for (int c = threadIdx.x; c < tile.nchunks; c += BLOCK) {
-                const auto a = gbl(Fp->anchor + 3 * (int64_t)(tile.chunk0 + c));
-                const double a0 = a[0], a1 = a[1], a2 = a[2];
-                const double o0 = a0 - Fp->src_origin[0], o1 = a1 - Fp->src_origin[1], o2 = a2 - Fp->src_origin[2];
-                const double av[3] = {a0, a1, a2};
-                double ya[3];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    double fr;
-                    int32_t kb;
-                    ya[i] = anchor_split(P, av, i, top.r64, top.inv_r64, top.K0[i], &fr, &kb);
-                    sh.frac[3 * c + i] = fr;
-                    sh.frac32[3 * c + i] = (float)fr;
-                    sh.kb[3 * c + i] = kb;
-                    sh.za[3 * c + i] = (float)(P[3 * i] * o0 + P[3 * i + 1] * o1 + P[3 * i + 2] * o2);
-                }
-                if (validate) {
-                    sh.vc[3 * c + 0] = (float)(a0 - cs[0]);
-                    sh.vc[3 * c + 1] = (float)(a1 - cs[1]);
-                    sh.vc[3 * c + 2] = (float)(a2 - cs[2]);
-                }
-                if constexpr (SKIP) sh.reach[c] = chunk_reaches(Fp, P, ya, tile.chunk0 + c, L) ? 1 : 0;
-            }
-            __syncthreads();
-        } else if constexpr (SKIP) {
-            for (int c = threadIdx.x; c < tile.nchunks; c += BLOCK) {
-                const auto a = gbl(Fp->anchor + 3 * (int64_t)(tile.chunk0 + c));
-                double ya[3];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) ya[i] = fma(P[3 * i + 2], a[2], fma(P[3 * i + 1], a[1], P[3 * i] * a[0])) + P[9 + i];
-                sh.reach[c] = chunk_reaches(Fp, P, ya, tile.chunk0 + c, L) ? 1 : 0;
-            }
-            __syncthreads();
-        }
-        // the list of chunks to walk (kept in chunk order)
-        if (wave == 0) {
-            int cnt = 0;
-            int32_t pts = 0;   // per lane: points of the chunks this lane kept
-            for (int base = 0; base < tile.nchunks; base += 64) {
-                const int c = base + lane;
-                bool keep = c < tile.nchunks;
-                if constexpr (SKIP) keep = keep && sh.reach[c];
-                const uint64_t m = __ballot(keep);
-                if (keep) {
-                    sh.live[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = c;
-                    pts += (int32_t)min<int64_t>(kChunk, n - (int64_t)(tile.chunk0 + c) * kChunk);
-                }
-                cnt += __popcll(m);
-            }
-            pts = wave_sum(pts);
-            if (lane == 0) {
-                sh.nlive = cnt;
-                sh.walked = pts;
-            }
-        }
-        __syncthreads();
-        const int nlive = __builtin_amdgcn_readfirstlane(sh.nlive);
-        // ---------------------------------------------------------------- per-point work
+        // ---------------------------------------------------------------- per-tile state
         Acc<T, KAHAN, NT> acc;
         acc.zero();
         // points with a voxel and table lookups per level: per lane, or in the
         // compacted paths wave-uniform totals packed two levels per word (level l
-        // in bits 16 (l % 2) of word l / 2; a tile has fewer than 65536 points)
+        // in bits 16 (l % 2) of word l / 2; a tile has fewer than 65536 points);
+        // source points and chunks walked (uniform)
         int32_t inl[kMaxLevels] = {0, 0, 0, 0};
         int32_t prb[kMaxLevels] = {0, 0, 0, 0};
         uint32_t inl2[2] = {0u, 0u}, prb2[2] = {0u, 0u};
+        int32_t walked_pts = 0, walked_chunks = 0;
         double ge = 0.0;
         if constexpr (MODE == kBwd) ge = grad_e[tile.factor];
 
@@ -664,339 +605,410 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
 
         // the first level's probe constants, loaded once per tile (uniform)
         const ProbeLevel pl0(Fp->lv[0]);
-        // each wave walks list entries wave, wave + NW, ...; the next chunk's point
-        // is loaded before the current one is processed, so its latency overlaps
         // the source's positions as a buffer (3 x n_pad floats; sources hold fewer than 2^27 points)
         const __amdgpu_buffer_rsrc_t xr = raw_rsrc(Fp->dxyz, (uint32_t)(3 * n_pad * (int64_t)sizeof(float)));
         const int32_t n32 = (int32_t)n;
-        RawPoint<PREC> nxt;
-        if (wave < nlive) {
-            const int c0 = __builtin_amdgcn_readfirstlane(sh.live[wave]);
-            load_point<PREC>(Fp, xr, (uint32_t)(tile.chunk0 + c0) * kChunk, n_pad, (uint32_t)lane, nxt);
-        }
-        for (int j = wave; j < nlive; j += NW) {
-            const int c = __builtin_amdgcn_readfirstlane(sh.live[j]);
-            // point index (sources hold fewer than 2^31 points) and the chunk's
-            // point count (uniform: only a source's last chunk is partial)
-            const uint32_t base = (uint32_t)(tile.chunk0 + c) * kChunk;
-            const int32_t i = (int32_t)(base + (uint32_t)lane);
-            const bool live = lane < min(kChunk, n32 - (int32_t)base);
-            const RawPoint<PREC> cur = nxt;
-            if (j + NW < nlive) {
-                const int cn = __builtin_amdgcn_readfirstlane(sh.live[j + NW]);
-                load_point<PREC>(Fp, xr, (uint32_t)(tile.chunk0 + cn) * kChunk, n_pad, (uint32_t)lane, nxt);
-            }
-            if constexpr (CMP && PREC == kF64) {
-                // ---- FP64 mode: probe every point, queue its hits, drain full waves
-                HitQueue& Q = s_q[wave];
-                const double x0 = cur.x[0], x1 = cur.x[1], x2 = cur.x[2];
-                double yl[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) yl[a] = (R[3 * a] * x0 + R[3 * a + 1] * x1 + R[3 * a + 2] * x2) + tt[a];
-                bool vis = live;
-                if (live && validate) {
-                    const auto Nv = gbl(Fp->nrm64);
-                    const double sv = (x0 - cs[0]) * Nv[i] + (x1 - cs[1]) * Nv[n_pad + i] + (x2 - cs[2]) * Nv[2 * n_pad + i];
-                    vis = !(sv > 0.0);
-                }
-#pragma unroll
-                for (int l = 0; l < kMaxLevels; ++l) {
-                    if (l >= L) break;
-                    const LevelDesc& lv = Fp->lv[l];
-                    int32_t kq[3];
-                    bool in = vis;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const int64_t k = (int64_t)floor(yl[a] * lv.inv_r64) - lv.K0[a];
-                        in &= (k >= lv.kmin[a]) & (k <= lv.kmax[a]);
-                        kq[a] = (int32_t)k;
-                    }
-                    int32_t v = -1;
-                    prb2[l >> 1] += (uint32_t)__popcll(__ballot(in)) << (16 * (l & 1));
-                    if (in) v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
-                    const bool hit = v >= 0;
-                    const uint64_t mask = __ballot(hit);
-                    inl2[l >> 1] += (uint32_t)__popcll(mask) << (16 * (l & 1));
-                    const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                    if (hit) {
-                        const int e = (q_head + q_count + below) & (kQueue - 1);
-                        Q.pt[e] = (int32_t)i;
-                        Q.rec[e] = v;
-                        Q.cl[e] = (c << 2) | l;
-                    }
-                    q_count += __popcll(mask);
-                    if (q_count >= kChunk) {
-                        __builtin_amdgcn_wave_barrier();
-                        drain_hit<PREC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
-                        q_head = (q_head + kChunk) & (kQueue - 1);
-                        q_count -= kChunk;
-                        __builtin_amdgcn_wave_barrier();
-                    }
-                }
-                continue;
-            } else if constexpr (CMP) {
-                // ---- probe every point, queue its hits, drain full waves of hits
-                HitQueue& Q = s_q[wave];
-                const float dx = cur.x[0], dy = cur.x[1], dz = cur.x[2];
-                float yl[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    yl[a] = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
-                bool vis = live;
-                if (live && validate) {
-                    const auto Nv = gbl(Fp->nrm);
-                    const float sv = (sh.vc[3 * c + 0] + dx) * Nv[i] + (sh.vc[3 * c + 1] + dy) * Nv[n_pad + i] +
-                                     (sh.vc[3 * c + 2] + dz) * Nv[2 * n_pad + i];
-                    vis = !(sv > 0.0f);
-                }
-#pragma unroll
-                for (int l = 0; l < kMaxLevels; ++l) {
-                    if (l >= L) break;
-                    const LevelDesc& lv = Fp->lv[l];
-                    const ProbeLevel pl = l == 0 ? pl0 : ProbeLevel(lv);
-                    int32_t v = -1;
-                    // key (coarse anchor key times the level ratio, a shift) and the
-                    // bounding-box test as one unsigned compare per axis, no branches
-                    int32_t kq[3];
-                    bool in = vis;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        kq[a] = (int32_t)((uint32_t)sh.kb[3 * c + a] << pl.log2scale) + floor_i32(yl[a] * pl.inv_r);
-                        in &= (uint32_t)(kq[a] - pl.kbox0[a]) <= pl.kboxw[a];
-                    }
-                    prb2[l >> 1] += (uint32_t)__popcll(__ballot(in)) << (16 * (l & 1));
-                    if (in) v = lookup(pl.slots, pl.log2cap, kq[0], kq[1], kq[2]);
-                    const bool hit = v >= 0;
-                    const uint64_t mask = __ballot(hit);
-                    inl2[l >> 1] += (uint32_t)__popcll(mask) << (16 * (l & 1));
-                    const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                    if (hit) {
-                        const int e = (q_head + q_count + below) & (kQueue - 1);
-                        Q.x[e] = dx;
-                        Q.y[e] = dy;
-                        Q.z[e] = dz;
-                        Q.pt[e] = (int32_t)i;
-                        Q.rec[e] = v;
-                        Q.cl[e] = (c << 2) | l;
-                    }
-                    q_count += __popcll(mask);
-                    if (q_count >= kChunk) {
-                        __builtin_amdgcn_wave_barrier();
-                        drain_hit<PREC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
-                        q_head = (q_head + kChunk) & (kQueue - 1);
-                        q_count -= kChunk;
-                        __builtin_amdgcn_wave_barrier();
-                    }
-                }
-                continue;
-            }
-            if (!live) continue;
-            // ---- load the point, transform it
-            // yl: transformed position (kC32: relative to the anchor's coarse voxel corner)
-            T x[3], z[3];
-            T yl[3];          // transformed position (kC32: FP32, relative to the anchor's coarse voxel)
-            bool vis = true;
+        // The tile's chunks are taken in batches of up to kMaxTileChunks (the
+        // per-chunk data held in LDS); the lane sums run on across batches, so a
+        // tile of several batches is reduced once.
+        for (int sb0 = 0; sb0 < tile.nchunks; sb0 += kMaxTileChunks) {
+            const int nch = min(kMaxTileChunks, tile.nchunks - sb0);
+            const int chunk0 = tile.chunk0 + sb0;
+            // ---------------------------------------------------------------- prologue: chunk anchors (kC32)
             if constexpr (PREC == kC32) {
-                // Keys come from the FP32 position (its ~5e-7 m error only matters
-                // for points that close to a voxel face, where either voxel is a
-                // valid answer).  The residual d = mu~ - y cancels metre-scale
-                // positions down to centimetres, so for hits the offset from the
-                // anchor is rotated and placed relative to the voxel centre in FP64.
-                const float dx = cur.x[0], dy = cur.x[1], dz = cur.x[2];
+                const LevelDesc& top = Fp->lv[L - 1];
+                for (int c = threadIdx.x; c < nch; c += BLOCK) {
+                    const auto a = gbl(Fp->anchor + 3 * (int64_t)(chunk0 + c));
+                    const double a0 = a[0], a1 = a[1], a2 = a[2];
+                    const double o0 = a0 - Fp->src_origin[0], o1 = a1 - Fp->src_origin[1], o2 = a2 - Fp->src_origin[2];
+                    const double av[3] = {a0, a1, a2};
+                    double ya[3];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    yl[a] = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
-                    z[a] = sh.za[3 * c + a] + fmaf(R[3 * a + 2], dz, fmaf(R[3 * a + 1], dy, R[3 * a] * dx));
+                    for (int i = 0; i < 3; ++i) {
+                        double fr;
+                        int32_t kb;
+                        ya[i] = anchor_split(P, av, i, top.r64, top.inv_r64, top.K0[i], &fr, &kb);
+                        sh.frac[3 * c + i] = fr;
+                        sh.frac32[3 * c + i] = (float)fr;
+                        sh.kb[3 * c + i] = kb;
+                        sh.za[3 * c + i] = (float)(P[3 * i] * o0 + P[3 * i + 1] * o1 + P[3 * i + 2] * o2);
+                    }
+                    if (validate) {
+                        sh.vc[3 * c + 0] = (float)(a0 - cs[0]);
+                        sh.vc[3 * c + 1] = (float)(a1 - cs[1]);
+                        sh.vc[3 * c + 2] = (float)(a2 - cs[2]);
+                    }
+                    if constexpr (SKIP) sh.reach[c] = chunk_reaches(Fp, P, ya, chunk0 + c, L) ? 1 : 0;
                 }
-                x[0] = dx;
-                x[1] = dy;
-                x[2] = dz;
-                if (validate) {
-                    const auto Nv = gbl(Fp->nrm);
-                    const float s = (sh.vc[3 * c + 0] + dx) * Nv[i] + (sh.vc[3 * c + 1] + dy) * Nv[n_pad + i] +
-                                    (sh.vc[3 * c + 2] + dz) * Nv[2 * n_pad + i];
-                    vis = !(s > 0.0f);
-                }
-            } else if constexpr (PREC == kN32) {
+                __syncthreads();
+            } else if constexpr (SKIP) {
+                for (int c = threadIdx.x; c < nch; c += BLOCK) {
+                    const auto a = gbl(Fp->anchor + 3 * (int64_t)(chunk0 + c));
+                    double ya[3];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) x[a] = cur.x[a];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    z[a] = R[3 * a] * x[0] + R[3 * a + 1] * x[1] + R[3 * a + 2] * x[2];
-                    yl[a] = z[a] + tt[a];
+                    for (int i = 0; i < 3; ++i) ya[i] = fma(P[3 * i + 2], a[2], fma(P[3 * i + 1], a[1], P[3 * i] * a[0])) + P[9 + i];
+                    sh.reach[c] = chunk_reaches(Fp, P, ya, chunk0 + c, L) ? 1 : 0;
                 }
-                if (validate) {
-                    const auto Nv = gbl(Fp->nrm);
-                    const float s = (x[0] - (float)cs[0]) * Nv[i] + (x[1] - (float)cs[1]) * Nv[n_pad + i] +
-                                    (x[2] - (float)cs[2]) * Nv[2 * n_pad + i];
-                    vis = !(s > 0.0f);
+                __syncthreads();
+            }
+            // the list of chunks to walk (kept in chunk order)
+            if (wave == 0) {
+                int cnt = 0;
+                int32_t pts = 0;   // per lane: points of the chunks this lane kept
+                for (int base = 0; base < nch; base += 64) {
+                    const int c = base + lane;
+                    bool keep = c < nch;
+                    if constexpr (SKIP) keep = keep && sh.reach[c];
+                    const uint64_t m = __ballot(keep);
+                    if (keep) {
+                        sh.live[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = c;
+                        pts += (int32_t)min<int64_t>(kChunk, n - (int64_t)(chunk0 + c) * kChunk);
+                    }
+                    cnt += __popcll(m);
                 }
-            } else {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) x[a] = cur.x[a];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    z[a] = R[3 * a] * x[0] + R[3 * a + 1] * x[1] + R[3 * a + 2] * x[2];
-                    yl[a] = z[a] + tt[a];
-                }
-                if (validate) {
-                    const double s = (x[0] - cs[0]) * Fp->nrm64[i] + (x[1] - cs[1]) * Fp->nrm64[n_pad + i] +
-                                     (x[2] - cs[2]) * Fp->nrm64[2 * n_pad + i];
-                    vis = !(s > 0.0);
+                pts = wave_sum(pts);
+                if (lane == 0) {
+                    sh.nlive = cnt;
+                    sh.walked = pts;
                 }
             }
-            if (!vis) {
-                if constexpr (MODE == kBwd) {
-                    if (grad_points != nullptr) write_point_grad(Fp, i, grad_points, grad_slab, points_dtype, 0.0, 0.0, 0.0);
-                }
-                continue;
+            __syncthreads();
+            const int nlive = __builtin_amdgcn_readfirstlane(sh.nlive);
+            RawPoint<PREC> nxt;
+            if (wave < nlive) {
+                const int c0 = __builtin_amdgcn_readfirstlane(sh.live[wave]);
+                load_point<PREC>(Fp, xr, (uint32_t)(chunk0 + c0) * kChunk, n_pad, (uint32_t)lane, nxt);
             }
-            // ---- per level: key, probe, terms
-            // S = R C R^T, once per point (FP64 in the compensated mode, where the
-            // fused covariance and its inverse are formed in FP64: both covariances
-            // are near-singular, so FP32 rounding of either one would move W by
-            // ~1e-4 relative along the surface normal)
-            using TS = typename std::conditional<PREC == kC32, double, T>::type;
-            TS S[6];
-            bool haveS = false;
-            T gp[3] = {T(0), T(0), T(0)};
+            for (int j = wave; j < nlive; j += NW) {
+                const int c = __builtin_amdgcn_readfirstlane(sh.live[j]);
+                // point index (sources hold fewer than 2^31 points) and the chunk's
+                // point count (uniform: only a source's last chunk is partial)
+                const uint32_t base = (uint32_t)(chunk0 + c) * kChunk;
+                const int32_t i = (int32_t)(base + (uint32_t)lane);
+                const bool live = lane < min(kChunk, n32 - (int32_t)base);
+                const RawPoint<PREC> cur = nxt;
+                if (j + NW < nlive) {
+                    const int cn = __builtin_amdgcn_readfirstlane(sh.live[j + NW]);
+                    load_point<PREC>(Fp, xr, (uint32_t)(chunk0 + cn) * kChunk, n_pad, (uint32_t)lane, nxt);
+                }
+                if constexpr (CMP && PREC == kF64) {
+                    // ---- FP64 mode: probe every point, queue its hits, drain full waves
+                    HitQueue& Q = s_q[wave];
+                    const double x0 = cur.x[0], x1 = cur.x[1], x2 = cur.x[2];
+                    double yl[3];
 #pragma unroll
-            for (int l = 0; l < kMaxLevels; ++l) {
-                if (l >= L) break;
-                const LevelDesc& lv = Fp->lv[l];
-                // relative key; a key outside the level's key bounding box (which also
-                // covers keys outside the packable range) has no voxel and is not probed
-                int32_t kq[3];
-                bool in = true;
-                int32_t jk[3];
-                T pc[3];   // absolute position (kN32, kF64)
+                    for (int a = 0; a < 3; ++a) yl[a] = (R[3 * a] * x0 + R[3 * a + 1] * x1 + R[3 * a + 2] * x2) + tt[a];
+                    bool vis = live;
+                    if (live && validate) {
+                        const auto Nv = gbl(Fp->nrm64);
+                        const double sv = (x0 - cs[0]) * Nv[i] + (x1 - cs[1]) * Nv[n_pad + i] + (x2 - cs[2]) * Nv[2 * n_pad + i];
+                        vis = !(sv > 0.0);
+                    }
+#pragma unroll
+                    for (int l = 0; l < kMaxLevels; ++l) {
+                        if (l >= L) break;
+                        const LevelDesc& lv = Fp->lv[l];
+                        int32_t kq[3];
+                        bool in = vis;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const int64_t k = (int64_t)floor(yl[a] * lv.inv_r64) - lv.K0[a];
+                            in &= (k >= lv.kmin[a]) & (k <= lv.kmax[a]);
+                            kq[a] = (int32_t)k;
+                        }
+                        int32_t v = -1;
+                        prb2[l >> 1] += (uint32_t)__popcll(__ballot(in)) << (16 * (l & 1));
+                        if (in) v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
+                        const bool hit = v >= 0;
+                        const uint64_t mask = __ballot(hit);
+                        inl2[l >> 1] += (uint32_t)__popcll(mask) << (16 * (l & 1));
+                        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                        if (hit) {
+                            const int e = (q_head + q_count + below) & (kQueue - 1);
+                            Q.pt[e] = (int32_t)i;
+                            Q.rec[e] = v;
+                            Q.cl[e] = (c << 2) | l;
+                        }
+                        q_count += __popcll(mask);
+                        if (q_count >= kChunk) {
+                            __builtin_amdgcn_wave_barrier();
+                            drain_hit<PREC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
+                            q_head = (q_head + kChunk) & (kQueue - 1);
+                            q_count -= kChunk;
+                            __builtin_amdgcn_wave_barrier();
+                        }
+                    }
+                    continue;
+                } else if constexpr (CMP) {
+                    // ---- probe every point, queue its hits, drain full waves of hits
+                    HitQueue& Q = s_q[wave];
+                    const float dx = cur.x[0], dy = cur.x[1], dz = cur.x[2];
+                    float yl[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        yl[a] = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
+                    bool vis = live;
+                    if (live && validate) {
+                        const auto Nv = gbl(Fp->nrm);
+                        const float sv = (sh.vc[3 * c + 0] + dx) * Nv[i] + (sh.vc[3 * c + 1] + dy) * Nv[n_pad + i] +
+                                         (sh.vc[3 * c + 2] + dz) * Nv[2 * n_pad + i];
+                        vis = !(sv > 0.0f);
+                    }
+#pragma unroll
+                    for (int l = 0; l < kMaxLevels; ++l) {
+                        if (l >= L) break;
+                        const LevelDesc& lv = Fp->lv[l];
+                        const ProbeLevel pl = l == 0 ? pl0 : ProbeLevel(lv);
+                        int32_t v = -1;
+                        // key (coarse anchor key times the level ratio, a shift) and the
+                        // bounding-box test as one unsigned compare per axis, no branches
+                        int32_t kq[3];
+                        bool in = vis;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            kq[a] = (int32_t)((uint32_t)sh.kb[3 * c + a] << pl.log2scale) + floor_i32(yl[a] * pl.inv_r);
+                            in &= (uint32_t)(kq[a] - pl.kbox0[a]) <= pl.kboxw[a];
+                        }
+                        prb2[l >> 1] += (uint32_t)__popcll(__ballot(in)) << (16 * (l & 1));
+                        if (in) v = lookup(pl.slots, pl.log2cap, kq[0], kq[1], kq[2]);
+                        const bool hit = v >= 0;
+                        const uint64_t mask = __ballot(hit);
+                        inl2[l >> 1] += (uint32_t)__popcll(mask) << (16 * (l & 1));
+                        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                        if (hit) {
+                            const int e = (q_head + q_count + below) & (kQueue - 1);
+                            Q.x[e] = dx;
+                            Q.y[e] = dy;
+                            Q.z[e] = dz;
+                            Q.pt[e] = (int32_t)i;
+                            Q.rec[e] = v;
+                            Q.cl[e] = (c << 2) | l;
+                        }
+                        q_count += __popcll(mask);
+                        if (q_count >= kChunk) {
+                            __builtin_amdgcn_wave_barrier();
+                            drain_hit<PREC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
+                            q_head = (q_head + kChunk) & (kQueue - 1);
+                            q_count -= kChunk;
+                            __builtin_amdgcn_wave_barrier();
+                        }
+                    }
+                    continue;
+                }
+                if (!live) continue;
+                // ---- load the point, transform it
+                // yl: transformed position (kC32: relative to the anchor's coarse voxel corner)
+                T x[3], z[3];
+                T yl[3];          // transformed position (kC32: FP32, relative to the anchor's coarse voxel)
+                bool vis = true;
                 if constexpr (PREC == kC32) {
+                    // Keys come from the FP32 position (its ~5e-7 m error only matters
+                    // for points that close to a voxel face, where either voxel is a
+                    // valid answer).  The residual d = mu~ - y cancels metre-scale
+                    // positions down to centimetres, so for hits the offset from the
+                    // anchor is rotated and placed relative to the voxel centre in FP64.
+                    const float dx = cur.x[0], dy = cur.x[1], dz = cur.x[2];
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        jk[a] = floor_i32(yl[a] * lv.inv_r);
-                        kq[a] = (int32_t)((uint32_t)sh.kb[3 * c + a] << lv.log2scale) + jk[a];
-                        in &= (uint32_t)(kq[a] - lv.kbox0[a]) <= lv.kboxw[a];
+                        yl[a] = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
+                        z[a] = sh.za[3 * c + a] + fmaf(R[3 * a + 2], dz, fmaf(R[3 * a + 1], dy, R[3 * a] * dx));
+                    }
+                    x[0] = dx;
+                    x[1] = dy;
+                    x[2] = dz;
+                    if (validate) {
+                        const auto Nv = gbl(Fp->nrm);
+                        const float s = (sh.vc[3 * c + 0] + dx) * Nv[i] + (sh.vc[3 * c + 1] + dy) * Nv[n_pad + i] +
+                                        (sh.vc[3 * c + 2] + dz) * Nv[2 * n_pad + i];
+                        vis = !(s > 0.0f);
+                    }
+                } else if constexpr (PREC == kN32) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) x[a] = cur.x[a];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        z[a] = R[3 * a] * x[0] + R[3 * a + 1] * x[1] + R[3 * a + 2] * x[2];
+                        yl[a] = z[a] + tt[a];
+                    }
+                    if (validate) {
+                        const auto Nv = gbl(Fp->nrm);
+                        const float s = (x[0] - (float)cs[0]) * Nv[i] + (x[1] - (float)cs[1]) * Nv[n_pad + i] +
+                                        (x[2] - (float)cs[2]) * Nv[2 * n_pad + i];
+                        vis = !(s > 0.0f);
                     }
                 } else {
 #pragma unroll
+                    for (int a = 0; a < 3; ++a) x[a] = cur.x[a];
+#pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        int64_t k;
-                        if constexpr (PREC == kN32) k = (int64_t)floorf(yl[a] * lv.inv_r) - lv.K0[a];
-                        else k = (int64_t)floor(yl[a] * lv.inv_r64) - lv.K0[a];
-                        in &= (k >= lv.kmin[a]) & (k <= lv.kmax[a]);
-                        kq[a] = (int32_t)k;
-                        pc[a] = yl[a];
+                        z[a] = R[3 * a] * x[0] + R[3 * a + 1] * x[1] + R[3 * a + 2] * x[2];
+                        yl[a] = z[a] + tt[a];
+                    }
+                    if (validate) {
+                        const double s = (x[0] - cs[0]) * Fp->nrm64[i] + (x[1] - cs[1]) * Fp->nrm64[n_pad + i] +
+                                         (x[2] - cs[2]) * Fp->nrm64[2 * n_pad + i];
+                        vis = !(s > 0.0);
                     }
                 }
-                if (!in) continue;
-                prb[l] += 1;
-                const int32_t v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
-                if (v < 0) continue;
-                inl[l] += 1;
-                if constexpr (MODE == kCount) continue;
-                T mv[3];
-                T W[6];
-                if constexpr (PREC == kC32) {
-                    // the voxel record's loads are issued before the covariance's (first
-                    // hit only), so the two round trips overlap
-                    const float* rec = lv.rec32 + (int64_t)v * kRec32;
-                    const f32x4 q0 = *gbl(reinterpret_cast<const f32x4*>(rec));
-                    const auto c2 = gbl(reinterpret_cast<const f64x2*>(rec + 4));
-                    const f64x2 cva = c2[0], cvb = c2[1], cvc = c2[2];
-                    if (!haveS) {
-                        point_S<PREC>(Fp, i, n_pad, P, R, S);
-                        haveS = true;
+                if (!vis) {
+                    if constexpr (MODE == kBwd) {
+                        if (grad_points != nullptr) write_point_grad(Fp, i, grad_points, grad_slab, points_dtype, 0.0, 0.0, 0.0);
                     }
-                    mv[0] = q0.x; mv[1] = q0.y; mv[2] = q0.z;
-                    double M[6], W64[6];
-                    M[0] = cva.x + S[0];
-                    M[1] = cva.y + S[1];
-                    M[2] = cvb.x + S[2];
-                    M[3] = cvb.y + S[3];
-                    M[4] = cvc.x + S[4];
-                    M[5] = cvc.y + S[5];
-                    sym3_inverse(M, W64);
+                    continue;
+                }
+                // ---- per level: key, probe, terms
+                // S = R C R^T, once per point (FP64 in the compensated mode, where the
+                // fused covariance and its inverse are formed in FP64: both covariances
+                // are near-singular, so FP32 rounding of either one would move W by
+                // ~1e-4 relative along the surface normal)
+                using TS = typename std::conditional<PREC == kC32, double, T>::type;
+                TS S[6];
+                bool haveS = false;
+                T gp[3] = {T(0), T(0), T(0)};
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) W[k] = (float)W64[k];
-                } else {
-                    T cvv[6];
-                    if constexpr (PREC == kN32) {
-                        const auto r4 = gbl(reinterpret_cast<const f32x4*>(lv.recN + (int64_t)v * kRecN));
-                        const f32x4 q0 = r4[0], q1 = r4[1], q2 = r4[2];
-                        mv[0] = q0.x; mv[1] = q0.y; mv[2] = q0.z;
-                        cvv[0] = q0.w; cvv[1] = q1.x; cvv[2] = q1.y; cvv[3] = q1.z; cvv[4] = q1.w; cvv[5] = q2.x;
+                for (int l = 0; l < kMaxLevels; ++l) {
+                    if (l >= L) break;
+                    const LevelDesc& lv = Fp->lv[l];
+                    // relative key; a key outside the level's key bounding box (which also
+                    // covers keys outside the packable range) has no voxel and is not probed
+                    int32_t kq[3];
+                    bool in = true;
+                    int32_t jk[3];
+                    T pc[3];   // absolute position (kN32, kF64)
+                    if constexpr (PREC == kC32) {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            jk[a] = floor_i32(yl[a] * lv.inv_r);
+                            kq[a] = (int32_t)((uint32_t)sh.kb[3 * c + a] << lv.log2scale) + jk[a];
+                            in &= (uint32_t)(kq[a] - lv.kbox0[a]) <= lv.kboxw[a];
+                        }
                     } else {
-                        const auto r2 = gbl(reinterpret_cast<const f64x2*>(lv.rec64 + (int64_t)v * kRec64));
-                        const f64x2 q0 = r2[0], q1 = r2[1], q2 = r2[2], q3 = r2[3], q4 = r2[4];
-                        mv[0] = q0.x; mv[1] = q0.y; mv[2] = q1.x;
-                        cvv[0] = q1.y; cvv[1] = q2.x; cvv[2] = q2.y; cvv[3] = q3.x; cvv[4] = q3.y; cvv[5] = q4.x;
-                    }
-                    if (!haveS) {
-                        point_S<PREC>(Fp, i, n_pad, P, R, S);
-                        haveS = true;
-                    }
-                    T M[6];
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) M[k] = cvv[k] + S[k];
-                    sym3_inverse(M, W);
+                        for (int a = 0; a < 3; ++a) {
+                            int64_t k;
+                            if constexpr (PREC == kN32) k = (int64_t)floorf(yl[a] * lv.inv_r) - lv.K0[a];
+                            else k = (int64_t)floor(yl[a] * lv.inv_r64) - lv.K0[a];
+                            in &= (k >= lv.kmin[a]) & (k <= lv.kmax[a]);
+                            kq[a] = (int32_t)k;
+                            pc[a] = yl[a];
+                        }
+                    }
+                    if (!in) continue;
+                    prb[l] += 1;
+                    const int32_t v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
+                    if (v < 0) continue;
+                    inl[l] += 1;
+                    if constexpr (MODE == kCount) continue;
+                    T mv[3];
+                    T W[6];
+                    if constexpr (PREC == kC32) {
+                        // the voxel record's loads are issued before the covariance's (first
+                        // hit only), so the two round trips overlap
+                        const float* rec = lv.rec32 + (int64_t)v * kRec32;
+                        const f32x4 q0 = *gbl(reinterpret_cast<const f32x4*>(rec));
+                        const auto c2 = gbl(reinterpret_cast<const f64x2*>(rec + 4));
+                        const f64x2 cva = c2[0], cvb = c2[1], cvc = c2[2];
+                        if (!haveS) {
+                            point_S<PREC>(Fp, i, n_pad, P, R, S);
+                            haveS = true;
+                        }
+                        mv[0] = q0.x; mv[1] = q0.y; mv[2] = q0.z;
+                        double M[6], W64[6];
+                        M[0] = cva.x + S[0];
+                        M[1] = cva.y + S[1];
+                        M[2] = cvb.x + S[2];
+                        M[3] = cvb.y + S[3];
+                        M[4] = cvc.x + S[4];
+                        M[5] = cvc.y + S[5];
+                        sym3_inverse(M, W64);
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) W[k] = (float)W64[k];
+                    } else {
+                        T cvv[6];
+                        if constexpr (PREC == kN32) {
+                            const auto r4 = gbl(reinterpret_cast<const f32x4*>(lv.recN + (int64_t)v * kRecN));
+                            const f32x4 q0 = r4[0], q1 = r4[1], q2 = r4[2];
+                            mv[0] = q0.x; mv[1] = q0.y; mv[2] = q0.z;
+                            cvv[0] = q0.w; cvv[1] = q1.x; cvv[2] = q1.y; cvv[3] = q1.z; cvv[4] = q1.w; cvv[5] = q2.x;
+                        } else {
+                            const auto r2 = gbl(reinterpret_cast<const f64x2*>(lv.rec64 + (int64_t)v * kRec64));
+                            const f64x2 q0 = r2[0], q1 = r2[1], q2 = r2[2], q3 = r2[3], q4 = r2[4];
+                            mv[0] = q0.x; mv[1] = q0.y; mv[2] = q1.x;
+                            cvv[0] = q1.y; cvv[1] = q2.x; cvv[2] = q2.y; cvv[3] = q3.x; cvv[4] = q3.y; cvv[5] = q4.x;
+                        }
+                        if (!haveS) {
+                            point_S<PREC>(Fp, i, n_pad, P, R, S);
+                            haveS = true;
+                        }
+                        T M[6];
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) M[k] = cvv[k] + S[k];
+                        sym3_inverse(M, W);
+                    }
+                    T d[3];
+                    if constexpr (PREC == kC32) {
+                        // y relative to the centre of the voxel found above (FP64), then d = mu~ - y
+                        const double ddx = cur.x[0], ddy = cur.x[1], ddz = cur.x[2];
+                        const double half = 0.5 * lv.r64;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const double t = fma(P[3 * a + 2], ddz,
+                                                 fma(P[3 * a + 1], ddy, fma(P[3 * a], ddx, sh.frac[3 * c + a] - half)));
+                            d[a] = (float)((double)mv[a] - fma(-(double)jk[a], lv.r64, t));
+                        }
+                    } else {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) d[a] = mv[a] - pc[a];
+                    }
+                    if constexpr (MODE == kLin) {
+                        add_lin_terms(acc, d, W, z);
+                    } else if constexpr (MODE == kEval) {
+                        T u[3];
+                        sym3_mul(W, d, u);
+                        acc.add(0, d[0] * u[0] + d[1] * u[1] + d[2] * u[2]);
+                    } else {
+                        T u[3], Su[3], Sf[6];
+                        sym3_mul(W, d, u);
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) Sf[k] = (T)S[k];
+                        sym3_mul(Sf, u, Su);
+                        const T q0 = z[0] + Su[0], q1 = z[1] + Su[1], q2 = z[2] + Su[2];
+                        acc.add(0, T(2) * (u[1] * q2 - u[2] * q1));
+                        acc.add(1, T(2) * (u[2] * q0 - u[0] * q2));
+                        acc.add(2, T(2) * (u[0] * q1 - u[1] * q0));
+                        acc.add(3, T(-2) * u[0]);
+                        acc.add(4, T(-2) * u[1]);
+                        acc.add(5, T(-2) * u[2]);
+                        // de/dmu = -2 R^T u (source frame)
+                        gp[0] += T(-2) * (R[0] * u[0] + R[3] * u[1] + R[6] * u[2]);
+                        gp[1] += T(-2) * (R[1] * u[0] + R[4] * u[1] + R[7] * u[2]);
+                        gp[2] += T(-2) * (R[2] * u[0] + R[5] * u[1] + R[8] * u[2]);
+                    }
                 }
-                T d[3];
-                if constexpr (PREC == kC32) {
-                    // y relative to the centre of the voxel found above (FP64), then d = mu~ - y
-                    const double ddx = cur.x[0], ddy = cur.x[1], ddz = cur.x[2];
-                    const double half = 0.5 * lv.r64;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const double t = fma(P[3 * a + 2], ddz,
-                                             fma(P[3 * a + 1], ddy, fma(P[3 * a], ddx, sh.frac[3 * c + a] - half)));
-                        d[a] = (float)((double)mv[a] - fma(-(double)jk[a], lv.r64, t));
-                    }
-                } else {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) d[a] = mv[a] - pc[a];
-                }
-                if constexpr (MODE == kLin) {
-                    add_lin_terms(acc, d, W, z);
-                } else if constexpr (MODE == kEval) {
-                    T u[3];
-                    sym3_mul(W, d, u);
-                    acc.add(0, d[0] * u[0] + d[1] * u[1] + d[2] * u[2]);
-                } else {
-                    T u[3], Su[3], Sf[6];
-                    sym3_mul(W, d, u);
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) Sf[k] = (T)S[k];
-                    sym3_mul(Sf, u, Su);
-                    const T q0 = z[0] + Su[0], q1 = z[1] + Su[1], q2 = z[2] + Su[2];
-                    acc.add(0, T(2) * (u[1] * q2 - u[2] * q1));
-                    acc.add(1, T(2) * (u[2] * q0 - u[0] * q2));
-                    acc.add(2, T(2) * (u[0] * q1 - u[1] * q0));
-                    acc.add(3, T(-2) * u[0]);
-                    acc.add(4, T(-2) * u[1]);
-                    acc.add(5, T(-2) * u[2]);
-                    // de/dmu = -2 R^T u (source frame)
-                    gp[0] += T(-2) * (R[0] * u[0] + R[3] * u[1] + R[6] * u[2]);
-                    gp[1] += T(-2) * (R[1] * u[0] + R[4] * u[1] + R[7] * u[2]);
-                    gp[2] += T(-2) * (R[2] * u[0] + R[5] * u[1] + R[8] * u[2]);
+                if constexpr (MODE == kBwd) {
+                    if (grad_points != nullptr)
+                        write_point_grad(Fp, i, grad_points, grad_slab, points_dtype, ge * (double)gp[0],
+                                         ge * (double)gp[1], ge * (double)gp[2]);
                 }
             }
-            if constexpr (MODE == kBwd) {
-                if (grad_points != nullptr)
-                    write_point_grad(Fp, i, grad_points, grad_slab, points_dtype, ge * (double)gp[0],
-                                     ge * (double)gp[1], ge * (double)gp[2]);
-            }
-        }
-        if constexpr (CMP) {
-            // the last, partial wave of queued hits
-            if (q_count > 0) {
-                __builtin_amdgcn_wave_barrier();
-                if (lane < q_count) {
-                    drain_hit<PREC>(acc, Fp, sh, pl0, P, R, tt, n_pad, s_q[wave], (q_head + lane) & (kQueue - 1));
+            if constexpr (CMP) {
+                // the last, partial wave of queued hits (they refer to this batch's chunks)
+                if (q_count > 0) {
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane < q_count) {
+                        drain_hit<PREC>(acc, Fp, sh, pl0, P, R, tt, n_pad, s_q[wave], (q_head + lane) & (kQueue - 1));
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    q_head = (q_head + q_count) & (kQueue - 1);
+                    q_count = 0;
                 }
-                __builtin_amdgcn_wave_barrier();
             }
+            walked_pts += __builtin_amdgcn_readfirstlane(sh.walked);
+            walked_chunks += nlive;
+            __syncthreads();   // the next batch's prologue overwrites the chunk data
         }
         // ---------------------------------------------------------------- reduction of the tile
         // lanes -> wave -> tile: FP64 except kN32, which stays FP32 end to end
@@ -1036,9 +1048,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
             double s = 0.0;
             const bool inl_or_probe = (k >= kRowInl && k < kRowWalk) || (k >= kRowProbe && k < kRowChunks);
             if (k == kRowWalk) {
-                s = (double)sh.walked;
+                s = (double)walked_pts;
             } else if (k == kRowChunks) {
-                s = (double)nlive;
+                s = (double)walked_chunks;
             } else if (k >= kRowChunks + 1) {
                 s = 0.0;
             } else if (PREC == kN32 && k < kTerms) {

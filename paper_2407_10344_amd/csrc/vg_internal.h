@@ -35,7 +35,8 @@ constexpr int kRowProbe = kRowWalk + 1;          // 4: table lookups, per level
 constexpr int kRowChunks = kRowProbe + 4;        // 1: chunks walked
 constexpr int kRow = 40;
 constexpr int kWork = 8;                // per-factor work counts: walked points, walked chunks, lookups (4), 0, 0
-constexpr int kMaxTileChunks = 128;     // at most 8192 points per tile
+constexpr int kMaxTileChunks = 128;     // chunks whose data a tile holds in LDS at once
+constexpr int kMaxTilePoints = 32768;   // points per tile (taken in batches of kMaxTileChunks chunks)
 constexpr int kRec32 = 16;              // floats per compensated voxel record (64 B: 4 FP32 + 6 FP64)
 constexpr int kRecN = 12;               // floats per absolute-FP32 voxel record
 constexpr int kRec64 = 10;              // doubles per FP64 voxel record

@@ -54,6 +54,9 @@ B_KEY = 8                  # one hash slot per (point, level)
 B_HIT = 36                 # voxel mean (12) + covariance (24) per hit
 B_FACTOR = 48 + 344        # pose in + e/H/b/inliers out per factor
 COPY_BYTES = 1 << 30       # calibration copy for the memory counters
+# launch shapes the autotuner measured on an MI355X, per batch signature (read
+# by the library; a batch without an entry is tuned and its shape appended)
+TUNE_CACHE = os.path.join(ROOT, "paper_2407_10344_amd", "tuned_shapes.jsonl")
 
 
 def log(*a):
@@ -300,29 +303,35 @@ def _counter_means(dirs):
     return per
 
 
-def summarize_profiles(kt_dir, pmc_dirs, command, tile_points, tile_order, workload, warmup):
+def summarize_profiles(kt_dir, pmc_dirs, command, tile_points, tile_order, workload, warmup, block=0):
     """Text summary of one rocprofv3 kernel-trace run and several counter runs of
-    ``bench.py --profile-steps``.  Memory counters are scaled by what they read
-    for the calibration kernels of known traffic the profile run ends with: a
-    fill that writes COPY_BYTES, a sum that streams them, and a gather of 64-byte
-    rows in random order (reads COPY_BYTES of rows plus the 8-byte indices)."""
+    ``bench.py --profile-steps``.  Memory counters are read against the
+    calibration kernels of known traffic the profile run ends with: a fill that
+    writes COPY_BYTES, a sum that streams them, and a gather of 64-byte rows in
+    random order (COPY_BYTES of rows plus the 8-byte indices).  FETCH_SIZE
+    charges every read request 64 bytes: the streaming sum reads half its bytes
+    (its requests are 128 bytes), and the random 64-byte rows read about twice
+    theirs (a miss moves a whole 128-byte line, as two counted requests).  So
+    the tile kernel's DRAM reads lie between FETCH_SIZE (every request 64 bytes)
+    and twice it (every request 128 bytes)."""
     import csv
+    prefix = TILE_PREFIX + (" %d," % block if block else "")
     stats = []
     for f in _csvs(kt_dir, "_kernel_stats.csv"):
         stats += list(csv.DictReader(open(f)))
-    tile = [r for r in stats if r["Name"].startswith(TILE_PREFIX)]
+    tile = [r for r in stats if r["Name"].startswith(prefix)]
     if len(tile) != 1:
         raise SystemExit("expected one tile-kernel row in the kernel stats, found %d" % len(tile))
     tile = tile[0]
     durs = []
     for f in _csvs(kt_dir, "_kernel_trace.csv"):
         for r in csv.DictReader(open(f)):
-            if r["Kernel_Name"].startswith(TILE_PREFIX):
+            if r["Kernel_Name"].startswith(prefix):
                 durs.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
     durs = [d for _, d in sorted(durs)][warmup:]
     steady_ns = sum(durs) / max(len(durs), 1)
     per = _counter_means(pmc_dirs)
-    tiles = [k for k in per if k.startswith(TILE_PREFIX)]
+    tiles = [k for k in per if k.startswith(prefix)]
     if len(tiles) != 1:
         raise SystemExit("expected one tile kernel in the counter runs, found %s" % tiles)
     tk = per[tiles[0]]
@@ -371,15 +380,16 @@ def summarize_profiles(kt_dir, pmc_dirs, command, tile_points, tile_order, workl
         s_stream = kib / sum_fetch
         s_gather = gather_read_kib / gather_fetch if gather_fetch else None
         w_scale = kib / fill_write
-        lines += ["calibration_sum_fetch_kib: %.1f (streams %.1f KiB)" % (sum_fetch, kib),
-                  "calibration_gather_fetch_kib: %s (reads %.1f KiB in 64-byte rows + indices)" % (
-                      "%.1f" % gather_fetch if gather_fetch else "n/a", gather_read_kib),
+        lines += ["calibration_sum_fetch_kib: %.1f (streams %.1f KiB: 128-byte requests counted as 64)" % (
+                      sum_fetch, kib),
+                  "calibration_gather_fetch_kib: %s (%.1f KiB of 64-byte rows + indices: each row's miss moves a "
+                  "128-byte line)" % ("%.1f" % gather_fetch if gather_fetch else "n/a", gather_read_kib),
                   "calibration_fill_write_kib: %.1f (writes %.1f KiB)" % (fill_write, kib),
                   "fetch_scale_stream: %.4f" % s_stream,
                   "fetch_scale_gather: %s" % ("%.4f" % s_gather if s_gather else "n/a"),
                   "write_scale: %.4f" % w_scale]
-        lo = fetch * min(s_stream, s_gather or s_stream) * 1024.0 + write * w_scale * 1024.0
-        hi = fetch * max(s_stream, s_gather or s_stream) * 1024.0 + write * w_scale * 1024.0
+        lo = fetch * 1024.0 + write * w_scale * 1024.0
+        hi = fetch * s_stream * 1024.0 + write * w_scale * 1024.0
         lines += ["traffic_bytes_per_launch_range: %.6e %.6e (read requests all 64 B / all 128 B)" % (lo, hi)]
         rd = mean(tiles[0], "TCC_EA0_RDREQ_sum")
         r32 = mean(tiles[0], "TCC_EA0_RDREQ_32B_sum")
@@ -736,6 +746,7 @@ def main():
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp64"])
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-tune-cache", action="store_true", help="autotune from scratch (ignore the tuned shapes)")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0: library default / tuned)")
     ap.add_argument("--tile", type=int, default=0, help="source points per tile (0: default / tuned)")
     ap.add_argument("--bpc", type=int, default=0, help="persistent workgroups per CU (0: default / tuned)")
@@ -757,7 +768,8 @@ def main():
     if args.summarize_profiles:
         tag = "global submap batch, %d submaps" % args.submaps if args.workload == "global" else args.workload
         sys.stdout.write(summarize_profiles(args.summarize_profiles[0], args.summarize_profiles[1:],
-                                            args.profile_command, args.tile, args.tile_order or 1, tag, args.warmup))
+                                            args.profile_command, args.tile, args.tile_order or 1, tag, args.warmup,
+                                            args.block))
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)"
@@ -783,13 +795,14 @@ def main():
     ctx = vgicp.Context(0)
     t = time.time()
     shape = {"block": args.block, "tile": args.tile, "blocks_per_cu": args.bpc, "tile_order": args.tile_order}
+    tune_cache = None if any(shape.values()) or args.no_tune_cache else TUNE_CACHE
     maps, srcs, batch = vgicp.build_workload(ctx, cfg, precision=args.precision, use_graph=True,
-                                             lane_kahan=args.lane_kahan, **shape)
+                                             lane_kahan=args.lane_kahan, tune_cache=tune_cache, **shape)
     torch.cuda.synchronize()
     log("device maps/sources/batch built in %.1f s" % (time.time() - t))
     poses = vgicp.poses12(np.array(cfg["poses"]))
     info = batch.info()
-    if not args.no_tune and args.profile_steps == 0 and not any(shape.values()):
+    if not args.no_tune and not any(shape.values()):
         t = time.time()
         chosen = batch.tune(poses, reps=2)
         info = batch.info()

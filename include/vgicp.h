@@ -321,10 +321,13 @@ vg_status vg_batch_work(vg_batch* batch, int64_t* walked_points, int64_t* walked
  * fastest is kept for this batch (candidates are visited in a fixed order of
  * preference and a later one wins only when faster by more than 1.5 %, so the
  * choice is stable under timing noise) and, when the batch was created with a
- * tune_cache path, appended to that file under a key made of the device name
- * and the batch signature (precision, F, total points, levels, validation).
+ * tune_cache path, appended to that file under a key made of the device
+ * (architecture, compute units) and the batch signature (precision, F, total
+ * points, levels, validation).
  * chosen (may be NULL) receives {block_threads, tile_points, blocks_per_cu,
- * tile_order}.  Both tile orders are candidates.  A batch created with
+ * tile_order}.  Both tile orders are candidates.  When the batch's tune_cache
+ * already holds a shape for this device and batch signature, that shape is
+ * applied without timing anything.  A batch created with
  * plain_per_factor is tuned for its own loop instead: tile points x block
  * threads candidates, each timed over whole calls of that loop (so a single
  * factor's launch can fill the device with small tiles). */

@@ -697,8 +697,10 @@ int default_blocks_per_cu(int block) { return std::max(1, 2048 / block); }
 
 std::string tune_key(const vg_batch* b) {
     std::ostringstream k;
-    k << b->ctx->name << "|" << b->ctx->arch << "|p" << b->opt.precision << "|F" << b->F << "|N" << b->total_points
-      << "|L" << b->L << "|v" << b->opt.surface_validation;
+    // the device by architecture and compute-unit count (its marketing name is not
+    // always available to the runtime)
+    k << b->ctx->arch << "|cu" << b->ctx->num_cu << "|p" << b->opt.precision << "|F" << b->F << "|N"
+      << b->total_points << "|L" << b->L << "|v" << b->opt.surface_validation;
     return k.str();
 }
 
@@ -1390,6 +1392,26 @@ extern "C" vg_status vg_batch_tune(vg_batch* b, const double* poses, int32_t rep
     hipStream_t st = b->ctx->stream;
     std::memcpy(b->h_poses, poses, sizeof(double) * 12 * b->F);
     VG_HIP(hipMemcpyAsync(b->d_poses, b->h_poses, sizeof(double) * 12 * b->F, hipMemcpyHostToDevice, st));
+    {
+        // a shape already recorded in the tune cache for this device and batch signature
+        int bl = 0, tp = 0, bc = 0, to = 0;
+        if (!b->opt.plain_per_factor && tune_lookup(b, &bl, &tp, &bc, &to) && valid_shape(bl, tp, bc) &&
+            (to == 1 || to == 2)) {
+            b->block = bl;
+            b->tile_points = tp;
+            b->blocks_per_cu = bc;
+            b->tile_order = to;
+            build_tiles(b);
+            VG_TRY(upload_schedule(b));
+            if (chosen) {
+                chosen[0] = bl;
+                chosen[1] = tp;
+                chosen[2] = bc;
+                chosen[3] = to;
+            }
+            return VG_OK;
+        }
+    }
     if (b->opt.plain_per_factor) {
         // the per-factor loop: every factor is its own launch, so its tiles must
         // be small enough to fill the device on their own; each candidate is

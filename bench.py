@@ -394,13 +394,14 @@ def summarize_profiles(kt_dir, pmc_dirs, command, tile_points, tile_order, workl
         rd = mean(tiles[0], "TCC_EA0_RDREQ_sum")
         r32 = mean(tiles[0], "TCC_EA0_RDREQ_32B_sum")
         r128 = mean(tiles[0], "TCC_BUBBLE_sum")
-        if rd is not None and r32 is not None and r128 is not None and r128 > 0:
+        if rd is not None and r32 is not None and r128 is not None and r128 > 0.01 * rd:
             exact = 128.0 * r128 + 64.0 * (rd - r128 - r32) + 32.0 * r32 + write * w_scale * 1024.0
             lines.append("traffic_bytes_per_launch: %.6e (read requests by size: 128 B %.4g, 32 B %.4g, 64 B the rest)"
                          % (exact, r128, r32))
         else:
             lines.append("traffic_bytes_per_launch: %.6e (midpoint of the range: the 128-byte request counter "
-                         "reads 0 here, so the split of requests by size is unknown)" % ((lo + hi) / 2))
+                         "reads %s here, so the split of requests by size is unknown)" % (
+                             (lo + hi) / 2, "n/a" if r128 is None else "%.3g" % r128))
     hit, miss = mean(tiles[0], "TCC_HIT_sum"), mean(tiles[0], "TCC_MISS_sum")
     if hit is not None and miss is not None and hit + miss > 0:
         lines.append("l2_hit_rate: %.4f" % (hit / (hit + miss)))

@@ -37,17 +37,15 @@ __host__ __device__ __forceinline__ void unpack_key(uint64_t p, int64_t k[3]) {
     k[2] = (int64_t)(p & m) - kKeyBias;
 }
 
-// Slot of a block (block coordinates bx, by, bz, 12 bits each): Fibonacci
-// hashing (the top bits of one 32-bit product with the golden-ratio constant)
-// of the coordinates folded into one word.  The block key packs the same
-// coordinates into 36 bits.
-__host__ __device__ __forceinline__ uint32_t slot_of_block(uint32_t bx, uint32_t by, uint32_t bz, uint32_t log2cap) {
-    return (((bx << 20) ^ (by << 10) ^ bz) * 0x9E3779B1u) >> (32u - log2cap);
+// Slot of a block: Fibonacci hashing (the top bits of one 32-bit product with
+// the golden-ratio constant) of the block key (bx << 24 | by << 12 | bz, 12
+// bits per coordinate, 36 bits) folded into one word by XOR of its two words,
+// which the lookup forms anyway for the key compare.
+__host__ __device__ __forceinline__ uint32_t slot_of_words(uint32_t lo, uint32_t hi, uint32_t log2cap) {
+    return ((lo ^ hi) * 0x9E3779B1u) >> (32u - log2cap);
 }
 __host__ __device__ __forceinline__ uint32_t slot_of(uint64_t bk, uint32_t log2cap) {
-    const uint32_t m = (1u << kBlockBits) - 1u;
-    return slot_of_block((uint32_t)(bk >> (2 * kBlockBits)) & m, (uint32_t)(bk >> kBlockBits) & m, (uint32_t)bk & m,
-                         log2cap);
+    return slot_of_words((uint32_t)bk, (uint32_t)(bk >> 32), log2cap);
 }
 
 // Sparse-block voxel lookup.  Voxels are grouped in 4 x 4 x 4 blocks; a hash
@@ -74,17 +72,26 @@ __device__ __forceinline__ T load_off(const void* base, uint32_t byte_off) {
     return *gbl(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint64_t)byte_off));
 }
 
-// Record index of relative key (kx, ky, kz) (each in [-8192, 8191]), or -1.
-// The first table entry decides almost every lookup (load factor <= 1/4): it
-// is either the block, or empty, or (rarely) another block, and only then is
-// the chain walked.  The occupancy test and the popcount below the voxel's bit
-// take no branch on which half of the mask holds the bit.
-__device__ __forceinline__ int32_t lookup(const uint64_t* __restrict__ slots, uint32_t log2cap, int32_t kx,
-                                          int32_t ky, int32_t kz) {
-    const uint32_t ux = (uint32_t)(kx + kKeyBias), uy = (uint32_t)(ky + kKeyBias), uz = (uint32_t)(kz + kKeyBias);
+// (a & M) | (b & ~M) for a small constant mask M, as one v_bfi_b32
+template <uint32_t M>
+__device__ __forceinline__ uint32_t bfi_low(uint32_t a, uint32_t b) {
+    static_assert(M <= 64, "an inline constant");
+    uint32_t r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "n"(M), "v"(a), "v"(b));
+    return r;
+}
+
+// Record index of the voxel with biased key (ux, uy, uz) = relative key + 8192
+// (each in [0, 16383]), or -1.  The first table entry decides almost every
+// lookup (load factor <= 1/4): it is either the block, or empty, or (rarely)
+// another block, and only then is the chain walked.  The occupancy test and the
+// popcount below the voxel's bit work on the 64-bit mask as a whole.
+__device__ __forceinline__ int32_t lookup_u(const uint64_t* __restrict__ slots, uint32_t log2cap, uint32_t ux,
+                                            uint32_t uy, uint32_t uz) {
     const uint32_t bx = ux >> kBlockShift, by = uy >> kBlockShift, bz = uz >> kBlockShift;
-    const uint64_t bk = ((uint64_t)bx << (2 * kBlockBits)) | (uint64_t)((by << kBlockBits) | bz);
-    uint32_t h = slot_of_block(bx, by, bz, log2cap);
+    const uint32_t klo = (bx << (2 * kBlockBits)) | (by << kBlockBits) | bz, khi = bx >> (32 - 2 * kBlockBits);
+    const uint64_t bk = ((uint64_t)khi << 32) | klo;
+    uint32_t h = slot_of_words(klo, khi, log2cap);
     u64x2 e = load_off<u64x2>(slots, h << 4);
     bool same = (e.x >> kBaseBits) == bk;
     if (!same && e.x != kEmpty) {
@@ -98,15 +105,24 @@ __device__ __forceinline__ int32_t lookup(const uint64_t* __restrict__ slots, ui
         }
     }
     // an empty entry never holds the block (a valid entry word is never all ones)
-    const uint32_t local = (ux & 3u) | ((uy & 3u) << 2) | ((uz & 3u) << 4);
-    const bool upper = (uz & 2u) != 0u;   // bit 32..63 of the mask
-    const uint32_t sh = local & 31u;
-    const uint32_t lo = (uint32_t)e.y, hi = (uint32_t)(e.y >> 32);
-    const bool occupied = (((upper ? hi : lo) >> sh) & 1u) != 0u;
-    const uint32_t below_mask = (1u << sh) - 1u;
-    const uint32_t below = __popc(lo & (upper ? ~0u : below_mask)) + __popc(hi & (upper ? below_mask : 0u));
-    const int32_t rec = (int32_t)((uint32_t)e.x & (uint32_t)kBaseMask) + (int32_t)below;
-    return (same && e.x != kEmpty && occupied) ? rec : -1;
+    // bit of the voxel in the mask: x + 4 y + 16 z of its position in the block
+    // (two bit-field inserts; bits above 5 are left over from z, and the 64-bit
+    // shifts below read only bits 0..5 of their shift operand)
+    const uint32_t local = bfi_low<15u>(bfi_low<3u>(ux, uy << 2), uz << 4) & 63u;
+    const uint64_t m = e.y;
+    const bool occupied = ((m >> local) & 1ull) != 0ull;
+    // record = first record of the block + occupied voxels below this one
+    const uint64_t below = m & ~(~0ull << local);
+    uint32_t rec = (uint32_t)e.x & (uint32_t)kBaseMask;
+    rec += (uint32_t)__popc((uint32_t)below);
+    rec += (uint32_t)__popc((uint32_t)(below >> 32));
+    return (same && e.x != kEmpty && occupied) ? (int32_t)rec : -1;
+}
+
+// The same for a relative key (kx, ky, kz) (each in [-8192, 8191]).
+__device__ __forceinline__ int32_t lookup(const uint64_t* __restrict__ slots, uint32_t log2cap, int32_t kx,
+                                          int32_t ky, int32_t kz) {
+    return lookup_u(slots, log2cap, (uint32_t)(kx + kKeyBias), (uint32_t)(ky + kKeyBias), (uint32_t)(kz + kKeyBias));
 }
 
 // Buffer resource over `bytes` bytes at p (raw buffer, no swizzle): loads

@@ -179,32 +179,39 @@ __device__ __forceinline__ void add_lin_terms(A& acc, const T d[3], const T w[6]
 }
 
 // The fields of one level that the probe reads for every chunk.
+// Keys are formed biased by 8192 (the lookup's unsigned form): the coarse
+// anchor key kb of a chunk becomes (kb + (8192 >> s)) << s at a level s
+// halvings finer, and the key box's corner is biased the same way.
 struct ProbeLevel {
     const uint64_t* slots;
     uint32_t log2cap, log2scale;
+    uint32_t kbias;       // 8192 >> log2scale
     float inv_r;
-    int32_t kbox0[3];
+    uint32_t kbox0u[3];   // key box corner + 8192
     uint32_t kboxw[3];
     const float* rec32;   // read by the hit terms of the first level
     double r64;
     __device__ __forceinline__ explicit ProbeLevel(const LevelDesc& lv)
-        : slots(lv.slots), log2cap(lv.log2cap), log2scale((uint32_t)lv.log2scale), inv_r(lv.inv_r),
-          kbox0{lv.kbox0[0], lv.kbox0[1], lv.kbox0[2]}, kboxw{lv.kboxw[0], lv.kboxw[1], lv.kboxw[2]},
-          rec32(lv.rec32), r64(lv.r64) {}
+        : slots(lv.slots), log2cap(lv.log2cap), log2scale((uint32_t)lv.log2scale),
+          kbias((uint32_t)kKeyBias >> (uint32_t)lv.log2scale), inv_r(lv.inv_r),
+          kbox0u{(uint32_t)(lv.kbox0[0] + kKeyBias), (uint32_t)(lv.kbox0[1] + kKeyBias),
+                 (uint32_t)(lv.kbox0[2] + kKeyBias)},
+          kboxw{lv.kboxw[0], lv.kboxw[1], lv.kboxw[2]}, rec32(lv.rec32), r64(lv.r64) {}
 };
 
 // Per-tile chunk data in LDS.  At 4 waves per SIMD a CU holds at most 16
 // waves, so even one-wave workgroups need at most 16 x 9 KB of the 160 KB.
 struct TileShared {
-    double frac[kMaxTileChunks * 3];   // anchor position inside its coarse voxel, FP64 (kC32)
-    float frac32[kMaxTileChunks * 3];  // the same rounded to FP32 (voxel keys)
-    int32_t kb[kMaxTileChunks * 3];    // coarse relative key of the anchor
+    double frac[kMaxTileChunks * 3];   // anchor position inside its coarse voxel, FP64 (kC32; minus r/2 in
+                                       // one-level compacted kernels)
+    float frac32[kMaxTileChunks * 3];  // the same rounded to FP32 (voxel keys; in voxel units in those kernels)
+    int32_t kb[kMaxTileChunks * 3];    // coarse relative key of the anchor (biased by 8192 in one-level kernels)
     float za[kMaxTileChunks * 3];      // R (anchor - o_s)
     float vc[kMaxTileChunks * 3];      // anchor - T^-1 c (surface validation)
     int32_t live[kMaxTileChunks];      // the chunks the waves walk, in chunk order
     int32_t nlive;
     int32_t walked;                    // source points in those chunks
-    uint8_t reach[kMaxTileChunks];     // chunk can reach a level's key box
+    uint8_t reach[kMaxTileChunks];     // kChunkCulled / kChunkStraddles / kChunkInside
 };
 
 // Per-wave queue of (point, level) hits of the compacted linearization: the
@@ -283,7 +290,10 @@ __device__ __forceinline__ void point_S(const FactorDesc* __restrict__ Fp, int64
 
 // Terms of one queued hit (compensated mode): the same arithmetic as the
 // uncompacted path, with the point's chunk and level taken from the entry.
-template <typename A>
+// SC (one-level kernels): R is the rotation scaled by 1/r and the chunk data
+// hold the anchor remainder scaled by 1/r (FP32, for the key) and minus r/2
+// (FP64, for the residual); the lever arm comes from the FP64 rotated offset.
+template <bool SC, typename A>
 __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restrict__ Fp, const TileShared& sh,
                                               const ProbeLevel& pl0, const double* P, const float* R, int64_t n_pad,
                                               float dx, float dy, float dz, int32_t i, int32_t v, int32_t cl) {
@@ -293,7 +303,7 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
     const float* rec_base = pl0.rec32;
     float inv_r = pl0.inv_r;
     double r64 = pl0.r64;
-    if (l != 0) {
+    if (!SC && l != 0) {
         const LevelDesc& lv = Fp->lv[l];
         rec_base = lv.rec32;
         inv_r = lv.inv_r;
@@ -310,8 +320,8 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float yl = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
-        jk[a] = floor_i32(yl * inv_r);
-        z[a] = sh.za[3 * c + a] + fmaf(R[3 * a + 2], dz, fmaf(R[3 * a + 1], dy, R[3 * a] * dx));
+        jk[a] = floor_i32(SC ? yl : yl * inv_r);
+        if (!SC) z[a] = sh.za[3 * c + a] + fmaf(R[3 * a + 2], dz, fmaf(R[3 * a + 1], dy, R[3 * a] * dx));
     }
     double M[6], W64[6];
     M[0] = cva.x + S[0];
@@ -327,11 +337,20 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
     const float mv[3] = {q0.x, q0.y, q0.z};
     // y - voxel centre in FP64: (anchor remainder - r/2) + R offset - jk r (jk r exact)
     const double ddx = dx, ddy = dy, ddz = dz;
-    const double half = 0.5 * r64;
+    if constexpr (SC) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const double t = fma(P[3 * a + 2], ddz, fma(P[3 * a + 1], ddy, fma(P[3 * a], ddx, sh.frac[3 * c + a] - half)));
-        d[a] = (float)((double)mv[a] - fma(-(double)jk[a], r64, t));
+        for (int a = 0; a < 3; ++a) {
+            const double t0 = fma(P[3 * a + 2], ddz, fma(P[3 * a + 1], ddy, P[3 * a] * ddx));
+            z[a] = sh.za[3 * c + a] + (float)t0;
+            d[a] = (float)((double)mv[a] - fma(-(double)jk[a], r64, t0 + sh.frac[3 * c + a]));
+        }
+    } else {
+        const double half = 0.5 * r64;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double t = fma(P[3 * a + 2], ddz, fma(P[3 * a + 1], ddy, fma(P[3 * a], ddx, sh.frac[3 * c + a] - half)));
+            d[a] = (float)((double)mv[a] - fma(-(double)jk[a], r64, t));
+        }
     }
     add_lin_terms(acc, d, W, z);
 }
@@ -363,12 +382,12 @@ __device__ __forceinline__ void cmp_hit_terms64(A& acc, const FactorDesc* __rest
 }
 
 // One queued hit, by precision mode.
-template <int PREC, typename A, typename T>
+template <int PREC, bool SC, typename A, typename T>
 __device__ __forceinline__ void drain_hit(A& acc, const FactorDesc* __restrict__ Fp, const TileShared& sh,
                                           const ProbeLevel& pl0, const double* P, const T* R, const T* tt,
                                           int64_t n_pad, const HitQueue& Q, int e) {
     if constexpr (PREC == kC32)
-        cmp_hit_terms(acc, Fp, sh, pl0, P, R, n_pad, Q.x[e], Q.y[e], Q.z[e], Q.pt[e], Q.rec[e], Q.cl[e]);
+        cmp_hit_terms<SC>(acc, Fp, sh, pl0, P, R, n_pad, Q.x[e], Q.y[e], Q.z[e], Q.pt[e], Q.rec[e], Q.cl[e]);
     else
         cmp_hit_terms64(acc, Fp, P, R, tt, n_pad, Q.pt[e], Q.rec[e], Q.cl[e]);
 }
@@ -382,10 +401,14 @@ constexpr int waves_per_eu() { return (PREC == kF64 || KH) ? 1 : 4; }
 // the source frame, both stored with the chunk.  In the target frame (anchor
 // at ya) the ball keeps its radius and the box is covered by the axis-aligned
 // box of half extents |R| h.  A chunk whose ball or box misses the key box of
-// every level has no correspondence.  The margins (1e-3 m + 1e-5 relative)
-// cover FP32 key positions and the FP32 rounding of the stored offsets.
-__device__ __forceinline__ bool chunk_reaches(const FactorDesc* __restrict__ Fp, const double* P, const double ya[3],
-                                              int64_t cg, int L) {
+// every level has no correspondence (culled); a chunk whose ball lies inside
+// the key box of every level has no point outside them, so its points skip the
+// per-point box test.  The margins (1e-3 m + 1e-5 relative) cover FP32 key
+// positions and the FP32 rounding of the stored offsets.
+constexpr int kChunkCulled = 0, kChunkStraddles = 1, kChunkInside = 2;
+constexpr int kInsideFlag = 1 << 16;   // in a live-list entry: the chunk is inside every key box
+__device__ __forceinline__ int chunk_state(const FactorDesc* __restrict__ Fp, const double* P, const double ya[3],
+                                           int64_t cg, int L) {
     const auto cb = gbl(Fp->cbound + 8 * cg);
     const double rr = (double)cb[3] * (1.0 + 1e-5) + 1e-3;
     double yc[3], ex[3];
@@ -395,7 +418,7 @@ __device__ __forceinline__ bool chunk_reaches(const FactorDesc* __restrict__ Fp,
         ex[i] = (fabs(P[3 * i]) * cb[4] + fabs(P[3 * i + 1]) * cb[5] + fabs(P[3 * i + 2]) * cb[6]) * (1.0 + 1e-5) +
                 1e-3;
     }
-    bool reach = false;
+    bool reach = false, inside = true;
     for (int l = 0; l < L; ++l) {
         const LevelDesc& lv = Fp->lv[l];
         double d2 = 0.0;
@@ -405,10 +428,11 @@ __device__ __forceinline__ bool chunk_reaches(const FactorDesc* __restrict__ Fp,
             const double g = fmax(0.0, fmax(lv.blo[i] - ya[i], ya[i] - lv.bhi[i]));
             d2 += g * g;
             box = box && (yc[i] + ex[i] >= lv.blo[i]) && (yc[i] - ex[i] <= lv.bhi[i]);
+            inside = inside && (ya[i] - rr >= lv.blo[i]) && (ya[i] + rr <= lv.bhi[i]);
         }
         reach |= (d2 <= rr * rr) && box;
     }
-    return reach;
+    return !reach ? kChunkCulled : (inside ? kChunkInside : kChunkStraddles);
 }
 
 // Gradient of point i (internal order) of a factor: a source used by this
@@ -489,8 +513,10 @@ __global__ void k_stage_poses(int64_t F, const double* __restrict__ poses, float
 }
 
 // VAL: surface validation (a compile-time switch, so that batches without it
-// carry none of its state through the point loop)
-template <int MODE, int PREC, int BLOCK, bool KH, bool VAL>
+// carry none of its state through the point loop).  LM: the most levels the
+// point loop is compiled for (1 for single-level batches, whose kernel then
+// holds no state of the other levels; else kMaxLevels).
+template <int MODE, int PREC, int BLOCK, bool KH, bool VAL, int LM>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per_eu<PREC, KH>()))) void k_tiles(
     const FactorDesc* __restrict__ fac, const Tile* __restrict__ tiles, int32_t t_begin, int32_t t_end,
     const double* __restrict__ poses, const float* __restrict__ posef, double* __restrict__ partials,
@@ -507,6 +533,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
     // naive FP32 mode, whose absolute-coordinate keys can be off by more than
     // the culling margin far from the origin)
     constexpr bool SKIP = ((PREC == kC32 || PREC == kF64) && MODE != kBwd);
+    // a one-level kernel keeps the chunks' anchor keys biased by 8192 in LDS
+    // (its only level is the coarse one, so they are the lookup's keys as they are)
+    constexpr int32_t KBB = (LM == 1) ? kKeyBias : 0;
+    // one-level compacted linearization: positions in voxel units (the rotation
+    // and the anchor remainders scaled by 1/r), so keys need no multiply
+    constexpr bool SC = CMP && PREC == kC32 && LM == 1;
     __shared__ TileShared sh;
     using QueueT = typename std::conditional<CMP, HitQueue, int32_t>::type;
     __shared__ QueueT s_q[CMP ? NW : 1];
@@ -573,6 +605,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
             for (int k = 0; k < 9; ++k) R[k] = P[k];
 #pragma unroll
             for (int k = 0; k < 3; ++k) tt[k] = P[9 + k];
+        } else if constexpr (SC) {
+            // R / r (the map's one level), uniform
+            const double ir = Fp->lv[0].inv_r64;
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                R[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int((float)(P[k] * ir))));
+#pragma unroll
+            for (int k = 0; k < 3; ++k) tt[k] = 0.0f;
         } else {
             const float* Pf = posef + 16 * (int64_t)tile.factor;
 #pragma unroll
@@ -628,9 +668,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         double fr;
                         int32_t kb;
                         ya[i] = anchor_split(P, av, i, top.r64, top.inv_r64, top.K0[i], &fr, &kb);
-                        sh.frac[3 * c + i] = fr;
-                        sh.frac32[3 * c + i] = (float)fr;
-                        sh.kb[3 * c + i] = kb;
+                        if constexpr (SC) {
+                            sh.frac[3 * c + i] = fr - 0.5 * top.r64;
+                            sh.frac32[3 * c + i] = (float)(fr * top.inv_r64);
+                        } else {
+                            sh.frac[3 * c + i] = fr;
+                            sh.frac32[3 * c + i] = (float)fr;
+                        }
+                        sh.kb[3 * c + i] = kb + KBB;
                         sh.za[3 * c + i] = (float)(P[3 * i] * o0 + P[3 * i + 1] * o1 + P[3 * i + 2] * o2);
                     }
                     if (validate) {
@@ -638,7 +683,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         sh.vc[3 * c + 1] = (float)(a1 - cs[1]);
                         sh.vc[3 * c + 2] = (float)(a2 - cs[2]);
                     }
-                    if constexpr (SKIP) sh.reach[c] = chunk_reaches(Fp, P, ya, chunk0 + c, L) ? 1 : 0;
+                    if constexpr (SKIP) sh.reach[c] = (uint8_t)chunk_state(Fp, P, ya, chunk0 + c, L);
                 }
                 __syncthreads();
             } else if constexpr (SKIP) {
@@ -647,7 +692,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     double ya[3];
 #pragma unroll
                     for (int i = 0; i < 3; ++i) ya[i] = fma(P[3 * i + 2], a[2], fma(P[3 * i + 1], a[1], P[3 * i] * a[0])) + P[9 + i];
-                    sh.reach[c] = chunk_reaches(Fp, P, ya, chunk0 + c, L) ? 1 : 0;
+                    sh.reach[c] = (uint8_t)chunk_state(Fp, P, ya, chunk0 + c, L);
                 }
                 __syncthreads();
             }
@@ -658,11 +703,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 for (int base = 0; base < nch; base += 64) {
                     const int c = base + lane;
                     bool keep = c < nch;
-                    if constexpr (SKIP) keep = keep && sh.reach[c];
+                    int flag = 0;
+                    if constexpr (SKIP) {
+                        const int st = keep ? (int)sh.reach[c] : kChunkCulled;
+                        keep = st != kChunkCulled;
+                        flag = st == kChunkInside ? kInsideFlag : 0;
+                    }
                     const uint64_t m = __ballot(keep);
                     if (keep) {
                         sh.live[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = c;
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = c | flag;
                         pts += (int32_t)min<int64_t>(kChunk, n - (int64_t)(chunk0 + c) * kChunk);
                     }
                     cnt += __popcll(m);
@@ -675,22 +725,39 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
             }
             __syncthreads();
             const int nlive = __builtin_amdgcn_readfirstlane(sh.nlive);
-            RawPoint<PREC> nxt;
-            if (wave < nlive) {
-                const int c0 = __builtin_amdgcn_readfirstlane(sh.live[wave]);
-                load_point<PREC>(Fp, xr, (uint32_t)(chunk0 + c0) * kChunk, n_pad, (uint32_t)lane, nxt);
+            // this wave walks entries wave, wave + NW, ... of the list; with two or
+            // more waves they are at most 64, held one per lane and read by index
+            int32_t mylive = 0;
+            if constexpr (NW >= 2) {
+                const int jj = wave + NW * lane;
+                mylive = jj < nlive ? sh.live[jj] : 0;
             }
-            for (int j = wave; j < nlive; j += NW) {
-                const int c = __builtin_amdgcn_readfirstlane(sh.live[j]);
+            auto live_chunk = [&](int j, int k) -> int {
+                if constexpr (NW >= 2) return __builtin_amdgcn_readlane(mylive, k);
+                else return __builtin_amdgcn_readfirstlane(sh.live[j]);
+            };
+            RawPoint<PREC> nxt;
+            int cnext = 0;
+            if (wave < nlive) {
+                cnext = live_chunk(wave, 0);
+                load_point<PREC>(Fp, xr, (uint32_t)(chunk0 + (cnext & (kInsideFlag - 1))) * kChunk, n_pad,
+                                 (uint32_t)lane, nxt);
+            }
+            for (int j = wave, k = 0; j < nlive; j += NW, ++k) {
+                const int c = cnext & (kInsideFlag - 1);
+                // every point of the chunk is inside every level's key box (uniform)
+                const bool inside = (cnext & kInsideFlag) != 0;
                 // point index (sources hold fewer than 2^31 points) and the chunk's
                 // point count (uniform: only a source's last chunk is partial)
                 const uint32_t base = (uint32_t)(chunk0 + c) * kChunk;
                 const int32_t i = (int32_t)(base + (uint32_t)lane);
-                const bool live = lane < min(kChunk, n32 - (int32_t)base);
+                const int32_t npts = min(kChunk, n32 - (int32_t)base);
+                const bool live = lane < npts;
                 const RawPoint<PREC> cur = nxt;
                 if (j + NW < nlive) {
-                    const int cn = __builtin_amdgcn_readfirstlane(sh.live[j + NW]);
-                    load_point<PREC>(Fp, xr, (uint32_t)(chunk0 + cn) * kChunk, n_pad, (uint32_t)lane, nxt);
+                    cnext = live_chunk(j + NW, k + 1);
+                    load_point<PREC>(Fp, xr, (uint32_t)(chunk0 + (cnext & (kInsideFlag - 1))) * kChunk, n_pad,
+                                     (uint32_t)lane, nxt);
                 }
                 if constexpr (CMP && PREC == kF64) {
                     // ---- FP64 mode: probe every point, queue its hits, drain full waves
@@ -706,7 +773,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         vis = !(sv > 0.0);
                     }
 #pragma unroll
-                    for (int l = 0; l < kMaxLevels; ++l) {
+                    for (int l = 0; l < LM; ++l) {
                         if (l >= L) break;
                         const LevelDesc& lv = Fp->lv[l];
                         int32_t kq[3];
@@ -734,7 +801,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         q_count += __popcll(mask);
                         if (q_count >= kChunk) {
                             __builtin_amdgcn_wave_barrier();
-                            drain_hit<PREC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
+                            drain_hit<PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
                             q_head = (q_head + kChunk) & (kQueue - 1);
                             q_count -= kChunk;
                             __builtin_amdgcn_wave_barrier();
@@ -757,24 +824,36 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         vis = !(sv > 0.0f);
                     }
 #pragma unroll
-                    for (int l = 0; l < kMaxLevels; ++l) {
+                    for (int l = 0; l < LM; ++l) {
                         if (l >= L) break;
                         const LevelDesc& lv = Fp->lv[l];
                         const ProbeLevel pl = l == 0 ? pl0 : ProbeLevel(lv);
                         int32_t v = -1;
-                        // key (coarse anchor key times the level ratio, a shift) and the
+                        // biased key (coarse anchor key times the level ratio, a shift; a
+                        // one-level kernel's only level is the coarse one) and the
                         // bounding-box test as one unsigned compare per axis, no branches
-                        int32_t kq[3];
+                        uint32_t ku[3];
                         bool in = vis;
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
-                            kq[a] = (int32_t)((uint32_t)sh.kb[3 * c + a] << pl.log2scale) + floor_i32(yl[a] * pl.inv_r);
-                            in &= (uint32_t)(kq[a] - pl.kbox0[a]) <= pl.kboxw[a];
+                            const uint32_t fl = (uint32_t)floor_i32(SC ? yl[a] : yl[a] * pl.inv_r);
+                            if constexpr (LM == 1) ku[a] = (uint32_t)sh.kb[3 * c + a] + fl;
+                            else ku[a] = (((uint32_t)sh.kb[3 * c + a] + pl.kbias) << pl.log2scale) + fl;
                         }
-                        prb2[l >> 1] += (uint32_t)__popcll(__ballot(in)) << (16 * (l & 1));
-                        if (in) v = lookup(pl.slots, pl.log2cap, kq[0], kq[1], kq[2]);
+                        // table lookups: inside the key boxes every visible point looks up
+                        // (without validation, every point of the chunk: a uniform count)
+                        uint32_t nlook;
+                        if (inside) {
+                            nlook = validate ? (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in)) : (uint32_t)npts;
+                        } else {
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) in &= (ku[a] - pl.kbox0u[a]) <= pl.kboxw[a];
+                            nlook = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in));
+                        }
+                        prb2[l >> 1] += nlook << (16 * (l & 1));
+                        if (in) v = lookup_u(pl.slots, pl.log2cap, ku[0], ku[1], ku[2]);
                         const bool hit = v >= 0;
-                        const uint64_t mask = __ballot(hit);
+                        const uint64_t mask = __builtin_amdgcn_ballot_w64(hit);
                         inl2[l >> 1] += (uint32_t)__popcll(mask) << (16 * (l & 1));
                         const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -790,7 +869,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         q_count += __popcll(mask);
                         if (q_count >= kChunk) {
                             __builtin_amdgcn_wave_barrier();
-                            drain_hit<PREC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
+                            drain_hit<PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
                             q_head = (q_head + kChunk) & (kQueue - 1);
                             q_count -= kChunk;
                             __builtin_amdgcn_wave_barrier();
@@ -869,7 +948,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 bool haveS = false;
                 T gp[3] = {T(0), T(0), T(0)};
 #pragma unroll
-                for (int l = 0; l < kMaxLevels; ++l) {
+                for (int l = 0; l < LM; ++l) {
                     if (l >= L) break;
                     const LevelDesc& lv = Fp->lv[l];
                     // relative key; a key outside the level's key bounding box (which also
@@ -882,7 +961,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
                             jk[a] = floor_i32(yl[a] * lv.inv_r);
-                            kq[a] = (int32_t)((uint32_t)sh.kb[3 * c + a] << lv.log2scale) + jk[a];
+                            kq[a] = (int32_t)((uint32_t)(sh.kb[3 * c + a] - KBB) << lv.log2scale) + jk[a];
                             in &= (uint32_t)(kq[a] - lv.kbox0[a]) <= lv.kboxw[a];
                         }
                     } else {
@@ -999,7 +1078,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 if (q_count > 0) {
                     __builtin_amdgcn_wave_barrier();
                     if (lane < q_count) {
-                        drain_hit<PREC>(acc, Fp, sh, pl0, P, R, tt, n_pad, s_q[wave], (q_head + lane) & (kQueue - 1));
+                        drain_hit<PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, s_q[wave], (q_head + lane) & (kQueue - 1));
                     }
                     __builtin_amdgcn_wave_barrier();
                     q_head = (q_head + q_count) & (kQueue - 1);
@@ -1273,14 +1352,15 @@ __global__ void k_fill_zero(uint32_t* p, int64_t n_words) {
 
 // ---------------------------------------------------------------- host launchers
 
-template <int MODE, int PREC, bool KH, bool VAL>
+template <int MODE, int PREC, bool KH, bool VAL, int LM>
 static vg_status launch_tiles_v(vg_batch* b, const Workspace& ws, const double* d_poses, int32_t t0, int32_t t1,
                                 int grid, const double* d_grad_e, void* d_grad_points, int points_dtype) {
     hipStream_t st = b->ctx->stream;
-#define VG_LAUNCH(BS)                                                                                         \
-    k_tiles<MODE, PREC, BS, KH, VAL><<<grid, BS, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, ws.posef,     \
-                                                          ws.partials, ws.counter, d_grad_e, d_grad_points,    \
-                                                          b->d_gslab, points_dtype, b->tile_order == 2 ? 1 : 0)
+#define VG_LAUNCH(BS)                                                                                          \
+    k_tiles<MODE, PREC, BS, KH, VAL, LM><<<grid, BS, 0, st>>>(b->d_fac, b->d_tiles, t0, t1, d_poses, ws.posef, \
+                                                              ws.partials, ws.counter, d_grad_e,              \
+                                                              d_grad_points, b->d_gslab, points_dtype,        \
+                                                              b->tile_order == 2 ? 1 : 0)
     switch (b->block) {
         case 64: VG_LAUNCH(64); break;
         case 128: VG_LAUNCH(128); break;
@@ -1296,10 +1376,17 @@ template <int MODE, int PREC, bool KH>
 static vg_status launch_tiles_t(vg_batch* b, const Workspace& ws, const double* d_poses, int32_t t0, int32_t t1,
                                 int grid, const double* d_grad_e, void* d_grad_points, int points_dtype) {
     if (b->opt.surface_validation)
-        return launch_tiles_v<MODE, PREC, KH, true>(b, ws, d_poses, t0, t1, grid, d_grad_e, d_grad_points,
-                                                    points_dtype);
-    return launch_tiles_v<MODE, PREC, KH, false>(b, ws, d_poses, t0, t1, grid, d_grad_e, d_grad_points,
-                                                 points_dtype);
+        return launch_tiles_v<MODE, PREC, KH, true, kMaxLevels>(b, ws, d_poses, t0, t1, grid, d_grad_e,
+                                                                d_grad_points, points_dtype);
+    // single-level compensated batches without validation (the submap factors)
+    // get a kernel compiled for one level
+    if constexpr (PREC == kC32 && !KH) {
+        if (b->L == 1)
+            return launch_tiles_v<MODE, PREC, KH, false, 1>(b, ws, d_poses, t0, t1, grid, d_grad_e, d_grad_points,
+                                                            points_dtype);
+    }
+    return launch_tiles_v<MODE, PREC, KH, false, kMaxLevels>(b, ws, d_poses, t0, t1, grid, d_grad_e,
+                                                             d_grad_points, points_dtype);
 }
 
 vg_status launch_tiles(vg_batch* b, const Workspace& ws, int mode, const double* d_poses, int32_t t0, int32_t t1,

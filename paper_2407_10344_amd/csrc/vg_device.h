@@ -17,6 +17,7 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* gbl(const 
 // Native vector types for 16-byte loads through global pointers.
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x3 __attribute__((ext_vector_type(3)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // Relative voxel key (|k| < 8192 per axis) packed into 42 bits; x is the most
@@ -196,6 +197,45 @@ __device__ __forceinline__ void sym3_inverse(const T m[6], T w[6]) {
     w[3] = D * s;
     w[4] = E * s;
     w[5] = Fv * s;
+}
+
+// Inverse of a symmetric 3x3 matrix formed in FP64, rounded to FP32: the
+// adjugate and determinant in FP64, 1/det by the hardware reciprocal and one
+// Newton step (far below FP32 rounding).
+__device__ __forceinline__ void sym3_inverse_f32(const double m[6], float w[6]) {
+    const double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5];
+    const double A = d * f - e * e;
+    const double B = c * e - b * f;
+    const double C = b * e - c * d;
+    const double det = a * A + b * B + c * C;
+    double s = __builtin_amdgcn_rcp(det);
+    s = fma(s, fma(-det, s, 1.0), s);
+    w[0] = (float)(A * s);
+    w[1] = (float)(B * s);
+    w[2] = (float)(C * s);
+    w[3] = (float)((a * f - c * c) * s);
+    w[4] = (float)((b * c - a * e) * s);
+    w[5] = (float)((a * d - b * b) * s);
+}
+
+// M = R C R^T + D for symmetric C and D (6 entries each) and row-major R, D
+// added inside the last fused multiply-add of each entry.
+template <typename T>
+__device__ __forceinline__ void rotate_cov_add(const T R[9], const T c[6], const T D[6], T M[6]) {
+    T RC[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const T r0 = R[3 * i + 0], r1 = R[3 * i + 1], r2 = R[3 * i + 2];
+        RC[3 * i + 0] = r0 * c[0] + r1 * c[1] + r2 * c[2];
+        RC[3 * i + 1] = r0 * c[1] + r1 * c[3] + r2 * c[4];
+        RC[3 * i + 2] = r0 * c[2] + r1 * c[4] + r2 * c[5];
+    }
+    M[0] = fma(RC[0], R[0], fma(RC[1], R[1], fma(RC[2], R[2], D[0])));
+    M[1] = fma(RC[0], R[3], fma(RC[1], R[4], fma(RC[2], R[5], D[1])));
+    M[2] = fma(RC[0], R[6], fma(RC[1], R[7], fma(RC[2], R[8], D[2])));
+    M[3] = fma(RC[3], R[3], fma(RC[4], R[4], fma(RC[5], R[5], D[3])));
+    M[4] = fma(RC[3], R[6], fma(RC[4], R[7], fma(RC[5], R[8], D[4])));
+    M[5] = fma(RC[6], R[6], fma(RC[7], R[7], fma(RC[8], R[8], D[5])));
 }
 
 // S = R C R^T for symmetric C (6 entries) and row-major R; S returned as 6 entries.

@@ -67,6 +67,14 @@ struct Acc {
             s[k] += v;
         }
     }
+    // += a b + c d: two fused multiply-adds into the sum (one compensated add with Kahan)
+    __device__ __forceinline__ void add2(int k, T a, T b, T c2, T d) {
+        if constexpr (KAHAN) {
+            add(k, fma(a, b, c2 * d));
+        } else {
+            s[k] = fma(c2, d, fma(a, b, s[k]));
+        }
+    }
     __device__ __forceinline__ T get(int k) const {
         if constexpr (KAHAN) return s[k] - c[k];
         else return s[k];
@@ -140,18 +148,19 @@ template <typename T, typename A>
 __device__ __forceinline__ void add_lin_terms(A& acc, const T d[3], const T w[6], const T z[3]) {
     T u[3];
     sym3_mul(w, d, u);
-    acc.add(0, d[0] * u[0] + d[1] * u[1] + d[2] * u[2]);
+    acc.add2(0, d[0], u[0], d[1], u[1]);
+    acc.add(0, d[2] * u[2]);
     // P = (z)x W
     const T P00 = -z[2] * w[1] + z[1] * w[2], P01 = -z[2] * w[3] + z[1] * w[4], P02 = -z[2] * w[4] + z[1] * w[5];
     const T P10 = z[2] * w[0] - z[0] * w[2], P11 = z[2] * w[1] - z[0] * w[4], P12 = z[2] * w[2] - z[0] * w[5];
     const T P20 = -z[1] * w[0] + z[0] * w[1], P21 = -z[1] * w[1] + z[0] * w[3], P22 = -z[1] * w[2] + z[0] * w[4];
     // H''_ww = -P (z)x
-    acc.add(1 + tri(0, 0), -(P01 * z[2] - P02 * z[1]));
-    acc.add(1 + tri(0, 1), -(-P00 * z[2] + P02 * z[0]));
-    acc.add(1 + tri(0, 2), -(P00 * z[1] - P01 * z[0]));
-    acc.add(1 + tri(1, 1), -(-P10 * z[2] + P12 * z[0]));
-    acc.add(1 + tri(1, 2), -(P10 * z[1] - P11 * z[0]));
-    acc.add(1 + tri(2, 2), -(P20 * z[1] - P21 * z[0]));
+    acc.add2(1 + tri(0, 0), -P01, z[2], P02, z[1]);
+    acc.add2(1 + tri(0, 1), P00, z[2], -P02, z[0]);
+    acc.add2(1 + tri(0, 2), -P00, z[1], P01, z[0]);
+    acc.add2(1 + tri(1, 1), P10, z[2], -P12, z[0]);
+    acc.add2(1 + tri(1, 2), -P10, z[1], P11, z[0]);
+    acc.add2(1 + tri(2, 2), -P20, z[1], P21, z[0]);
     // H''_wv = P
     acc.add(1 + tri(0, 3), P00);
     acc.add(1 + tri(0, 4), P01);
@@ -170,9 +179,9 @@ __device__ __forceinline__ void add_lin_terms(A& acc, const T d[3], const T w[6]
     acc.add(1 + tri(4, 5), w[4]);
     acc.add(1 + tri(5, 5), w[5]);
     // b'' = [u x z; -u]
-    acc.add(22, u[1] * z[2] - u[2] * z[1]);
-    acc.add(23, u[2] * z[0] - u[0] * z[2]);
-    acc.add(24, u[0] * z[1] - u[1] * z[0]);
+    acc.add2(22, u[1], z[2], -u[2], z[1]);
+    acc.add2(23, u[2], z[0], -u[0], z[2]);
+    acc.add2(24, u[0], z[1], -u[1], z[0]);
     acc.add(25, -u[0]);
     acc.add(26, -u[1]);
     acc.add(27, -u[2]);
@@ -186,14 +195,14 @@ struct ProbeLevel {
     const uint64_t* slots;
     uint32_t log2cap, log2scale;
     uint32_t kbias;       // 8192 >> log2scale
-    float inv_r;
+    float inv_r, r;
     uint32_t kbox0u[3];   // key box corner + 8192
     uint32_t kboxw[3];
     const float* rec32;   // read by the hit terms of the first level
     double r64;
     __device__ __forceinline__ explicit ProbeLevel(const LevelDesc& lv)
         : slots(lv.slots), log2cap(lv.log2cap), log2scale((uint32_t)lv.log2scale),
-          kbias((uint32_t)kKeyBias >> (uint32_t)lv.log2scale), inv_r(lv.inv_r),
+          kbias((uint32_t)kKeyBias >> (uint32_t)lv.log2scale), inv_r(lv.inv_r), r(lv.r),
           kbox0u{(uint32_t)(lv.kbox0[0] + kKeyBias), (uint32_t)(lv.kbox0[1] + kKeyBias),
                  (uint32_t)(lv.kbox0[2] + kKeyBias)},
           kboxw{lv.kboxw[0], lv.kboxw[1], lv.kboxw[2]}, rec32(lv.rec32), r64(lv.r64) {}
@@ -201,13 +210,18 @@ struct ProbeLevel {
 
 // Per-tile chunk data in LDS.  At 4 waves per SIMD a CU holds at most 16
 // waves, so even one-wave workgroups need at most 16 x 9 KB of the 160 KB.
+// The FP32 data of one chunk, read together from one LDS address.
+struct ChunkLds {
+    float frac32[3];   // anchor position inside its coarse voxel, FP32 (voxel keys; in voxel units in one-level
+                       // compacted kernels)
+    int32_t kb[3];     // coarse relative key of the anchor (biased by 8192 in one-level kernels)
+    float za[3];       // R (anchor - o_s)
+    float vc[3];       // anchor - T^-1 c (surface validation)
+};
 struct TileShared {
     double frac[kMaxTileChunks * 3];   // anchor position inside its coarse voxel, FP64 (kC32; minus r/2 in
                                        // one-level compacted kernels)
-    float frac32[kMaxTileChunks * 3];  // the same rounded to FP32 (voxel keys; in voxel units in those kernels)
-    int32_t kb[kMaxTileChunks * 3];    // coarse relative key of the anchor (biased by 8192 in one-level kernels)
-    float za[kMaxTileChunks * 3];      // R (anchor - o_s)
-    float vc[kMaxTileChunks * 3];      // anchor - T^-1 c (surface validation)
+    ChunkLds cd[kMaxTileChunks];
     int32_t live[kMaxTileChunks];      // the chunks the waves walk, in chunk order
     int32_t nlive;
     int32_t walked;                    // source points in those chunks
@@ -290,20 +304,76 @@ __device__ __forceinline__ void point_S(const FactorDesc* __restrict__ Fp, int64
 
 // Terms of one queued hit (compensated mode): the same arithmetic as the
 // uncompacted path, with the point's chunk and level taken from the entry.
-// SC (one-level kernels): R is the rotation scaled by 1/r and the chunk data
-// hold the anchor remainder scaled by 1/r (FP32, for the key) and minus r/2
-// (FP64, for the residual); the lever arm comes from the FP64 rotated offset.
+// SC (one-level kernels): R is the rotation scaled by 1/r, the chunk data hold
+// the anchor remainder scaled by 1/r (FP32, for the key) and minus r/2 (FP64,
+// for the residual), and the entry holds the chunk's byte offset in the LDS
+// chunk array.  The fused covariance is formed with the voxel's covariance
+// added inside the rotation's last multiply-adds, and the residual as one FMA
+// chain starting from the voxel centre.
 template <bool SC, typename A>
 __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restrict__ Fp, const TileShared& sh,
                                               const ProbeLevel& pl0, const double* P, const float* R, int64_t n_pad,
                                               float dx, float dy, float dz, int32_t i, int32_t v, int32_t cl) {
+    if constexpr (SC) {
+        static_assert(sizeof(ChunkLds) == 48, "the FP64 remainders of a chunk sit at half its byte offset");
+        const ChunkLds& cd = *reinterpret_cast<const ChunkLds*>(reinterpret_cast<const char*>(sh.cd) + cl);
+        const double* fh = reinterpret_cast<const double*>(reinterpret_cast<const char*>(sh.frac) + (cl >> 1));
+        // the point's covariance (read only here: most points find no voxel) and
+        // the voxel record: all ten loads are issued before any result is used
+        const __amdgpu_buffer_rsrc_t cr = raw_rsrc(Fp->cov, (uint32_t)(6 * n_pad * (int64_t)sizeof(float)));
+        float C32[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) C32[k] = rsrc_load_f32(cr, (uint32_t)i * 4u, (uint32_t)(k * n_pad) * 4u);
+        const uint32_t ro = (uint32_t)v * (uint32_t)(kRec32 * sizeof(float));
+        const f32x3 q0 = load_off<f32x3>(pl0.rec32, ro);   // mean - centre (the count is not needed)
+        const f64x2 cva = load_off<f64x2>(pl0.rec32, ro + 16u), cvb = load_off<f64x2>(pl0.rec32, ro + 32u),
+                    cvc = load_off<f64x2>(pl0.rec32, ro + 48u);
+        // the chunk's data (LDS), read while the loads are in flight
+        float f32[3], za[3];
+        double fhv[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            f32[a] = cd.frac32[a];
+            za[a] = cd.za[a];
+            fhv[a] = fh[a];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        double C64[6], R64[9];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) C64[k] = (double)C32[k];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) R64[k] = P[k];
+        int32_t jk[3];
+        float z[3], d[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float yl = chunk_pos32(f32[a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
+            jk[a] = floor_i32(yl);
+            z[a] = fmaf(yl - f32[a], pl0.r, za[a]);
+        }
+        const double Ct[6] = {cva.x, cva.y, cvb.x, cvb.y, cvc.x, cvc.y};
+        double M[6];
+        rotate_cov_add(R64, C64, Ct, M);
+        float W[6];
+        sym3_inverse_f32(M, W);
+        // d = mu~ - y in FP64: (voxel mean - centre) - ((anchor remainder - r/2) - jk r + R offset)
+        const double ddx = dx, ddy = dy, ddz = dz;
+        const float mv[3] = {q0.x, q0.y, q0.z};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double base = fma(-(double)jk[a], pl0.r64, fhv[a]) - (double)mv[a];
+            d[a] = -(float)fma(P[3 * a + 2], ddz, fma(P[3 * a + 1], ddy, fma(P[3 * a], ddx, base)));
+        }
+        add_lin_terms(acc, d, W, z);
+        return;
+    }
     const int c = cl >> 2, l = cl & 3;
     // the level's record array, 1/r and r: the first level's come from scalar
     // registers, so its record gather does not wait on a descriptor load
     const float* rec_base = pl0.rec32;
     float inv_r = pl0.inv_r;
     double r64 = pl0.r64;
-    if (!SC && l != 0) {
+    if (l != 0) {
         const LevelDesc& lv = Fp->lv[l];
         rec_base = lv.rec32;
         inv_r = lv.inv_r;
@@ -319,9 +389,9 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
     float z[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float yl = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
-        jk[a] = floor_i32(SC ? yl : yl * inv_r);
-        if (!SC) z[a] = sh.za[3 * c + a] + fmaf(R[3 * a + 2], dz, fmaf(R[3 * a + 1], dy, R[3 * a] * dx));
+        const float yl = chunk_pos32(sh.cd[c].frac32[a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
+        jk[a] = floor_i32(yl * inv_r);
+        z[a] = sh.cd[c].za[a] + fmaf(R[3 * a + 2], dz, fmaf(R[3 * a + 1], dy, R[3 * a] * dx));
     }
     double M[6], W64[6];
     M[0] = cva.x + S[0];
@@ -337,20 +407,11 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
     const float mv[3] = {q0.x, q0.y, q0.z};
     // y - voxel centre in FP64: (anchor remainder - r/2) + R offset - jk r (jk r exact)
     const double ddx = dx, ddy = dy, ddz = dz;
-    if constexpr (SC) {
+    const double half = 0.5 * r64;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double t0 = fma(P[3 * a + 2], ddz, fma(P[3 * a + 1], ddy, P[3 * a] * ddx));
-            z[a] = sh.za[3 * c + a] + (float)t0;
-            d[a] = (float)((double)mv[a] - fma(-(double)jk[a], r64, t0 + sh.frac[3 * c + a]));
-        }
-    } else {
-        const double half = 0.5 * r64;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double t = fma(P[3 * a + 2], ddz, fma(P[3 * a + 1], ddy, fma(P[3 * a], ddx, sh.frac[3 * c + a] - half)));
-            d[a] = (float)((double)mv[a] - fma(-(double)jk[a], r64, t));
-        }
+    for (int a = 0; a < 3; ++a) {
+        const double t = fma(P[3 * a + 2], ddz, fma(P[3 * a + 1], ddy, fma(P[3 * a], ddx, sh.frac[3 * c + a] - half)));
+        d[a] = (float)((double)mv[a] - fma(-(double)jk[a], r64, t));
     }
     add_lin_terms(acc, d, W, z);
 }
@@ -517,7 +578,7 @@ __global__ void k_stage_poses(int64_t F, const double* __restrict__ poses, float
 // point loop is compiled for (1 for single-level batches, whose kernel then
 // holds no state of the other levels; else kMaxLevels).
 template <int MODE, int PREC, int BLOCK, bool KH, bool VAL, int LM>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per_eu<PREC, KH>()))) void k_tiles(
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per_eu<PREC, KH>(), waves_per_eu<PREC, KH>()))) void k_tiles(
     const FactorDesc* __restrict__ fac, const Tile* __restrict__ tiles, int32_t t_begin, int32_t t_end,
     const double* __restrict__ poses, const float* __restrict__ posef, double* __restrict__ partials,
     uint32_t* __restrict__ counter, const double* __restrict__ grad_e,
@@ -670,18 +731,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         ya[i] = anchor_split(P, av, i, top.r64, top.inv_r64, top.K0[i], &fr, &kb);
                         if constexpr (SC) {
                             sh.frac[3 * c + i] = fr - 0.5 * top.r64;
-                            sh.frac32[3 * c + i] = (float)(fr * top.inv_r64);
+                            sh.cd[c].frac32[i] = (float)(fr * top.inv_r64);
                         } else {
                             sh.frac[3 * c + i] = fr;
-                            sh.frac32[3 * c + i] = (float)fr;
+                            sh.cd[c].frac32[i] = (float)fr;
                         }
-                        sh.kb[3 * c + i] = kb + KBB;
-                        sh.za[3 * c + i] = (float)(P[3 * i] * o0 + P[3 * i + 1] * o1 + P[3 * i + 2] * o2);
+                        sh.cd[c].kb[i] = kb + KBB;
+                        sh.cd[c].za[i] = (float)(P[3 * i] * o0 + P[3 * i + 1] * o1 + P[3 * i + 2] * o2);
                     }
                     if (validate) {
-                        sh.vc[3 * c + 0] = (float)(a0 - cs[0]);
-                        sh.vc[3 * c + 1] = (float)(a1 - cs[1]);
-                        sh.vc[3 * c + 2] = (float)(a2 - cs[2]);
+                        sh.cd[c].vc[0] = (float)(a0 - cs[0]);
+                        sh.cd[c].vc[1] = (float)(a1 - cs[1]);
+                        sh.cd[c].vc[2] = (float)(a2 - cs[2]);
                     }
                     if constexpr (SKIP) sh.reach[c] = (uint8_t)chunk_state(Fp, P, ya, chunk0 + c, L);
                 }
@@ -815,12 +876,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     float yl[3];
 #pragma unroll
                     for (int a = 0; a < 3; ++a)
-                        yl[a] = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
+                        yl[a] = chunk_pos32(sh.cd[c].frac32[a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
                     bool vis = live;
                     if (live && validate) {
                         const auto Nv = gbl(Fp->nrm);
-                        const float sv = (sh.vc[3 * c + 0] + dx) * Nv[i] + (sh.vc[3 * c + 1] + dy) * Nv[n_pad + i] +
-                                         (sh.vc[3 * c + 2] + dz) * Nv[2 * n_pad + i];
+                        const float sv = (sh.cd[c].vc[0] + dx) * Nv[i] + (sh.cd[c].vc[1] + dy) * Nv[n_pad + i] +
+                                         (sh.cd[c].vc[2] + dz) * Nv[2 * n_pad + i];
                         vis = !(sv > 0.0f);
                     }
 #pragma unroll
@@ -837,8 +898,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
                             const uint32_t fl = (uint32_t)floor_i32(SC ? yl[a] : yl[a] * pl.inv_r);
-                            if constexpr (LM == 1) ku[a] = (uint32_t)sh.kb[3 * c + a] + fl;
-                            else ku[a] = (((uint32_t)sh.kb[3 * c + a] + pl.kbias) << pl.log2scale) + fl;
+                            if constexpr (LM == 1) ku[a] = (uint32_t)sh.cd[c].kb[a] + fl;
+                            else ku[a] = (((uint32_t)sh.cd[c].kb[a] + pl.kbias) << pl.log2scale) + fl;
                         }
                         // table lookups: inside the key boxes every visible point looks up
                         // (without validation, every point of the chunk: a uniform count)
@@ -864,7 +925,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                             Q.z[e] = dz;
                             Q.pt[e] = (int32_t)i;
                             Q.rec[e] = v;
-                            Q.cl[e] = (c << 2) | l;
+                            Q.cl[e] = SC ? c * (int)sizeof(ChunkLds) : (c << 2) | l;
                         }
                         q_count += __popcll(mask);
                         if (q_count >= kChunk) {
@@ -892,16 +953,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                     const float dx = cur.x[0], dy = cur.x[1], dz = cur.x[2];
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        yl[a] = chunk_pos32(sh.frac32[3 * c + a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
-                        z[a] = sh.za[3 * c + a] + fmaf(R[3 * a + 2], dz, fmaf(R[3 * a + 1], dy, R[3 * a] * dx));
+                        yl[a] = chunk_pos32(sh.cd[c].frac32[a], R[3 * a], R[3 * a + 1], R[3 * a + 2], dx, dy, dz);
+                        z[a] = sh.cd[c].za[a] + fmaf(R[3 * a + 2], dz, fmaf(R[3 * a + 1], dy, R[3 * a] * dx));
                     }
                     x[0] = dx;
                     x[1] = dy;
                     x[2] = dz;
                     if (validate) {
                         const auto Nv = gbl(Fp->nrm);
-                        const float s = (sh.vc[3 * c + 0] + dx) * Nv[i] + (sh.vc[3 * c + 1] + dy) * Nv[n_pad + i] +
-                                        (sh.vc[3 * c + 2] + dz) * Nv[2 * n_pad + i];
+                        const float s = (sh.cd[c].vc[0] + dx) * Nv[i] + (sh.cd[c].vc[1] + dy) * Nv[n_pad + i] +
+                                        (sh.cd[c].vc[2] + dz) * Nv[2 * n_pad + i];
                         vis = !(s > 0.0f);
                     }
                 } else if constexpr (PREC == kN32) {
@@ -961,7 +1022,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
                             jk[a] = floor_i32(yl[a] * lv.inv_r);
-                            kq[a] = (int32_t)((uint32_t)(sh.kb[3 * c + a] - KBB) << lv.log2scale) + jk[a];
+                            kq[a] = (int32_t)((uint32_t)(sh.cd[c].kb[a] - KBB) << lv.log2scale) + jk[a];
                             in &= (uint32_t)(kq[a] - lv.kbox0[a]) <= lv.kboxw[a];
                         }
                     } else {

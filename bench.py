@@ -938,8 +938,11 @@ def unique_footprint(cfg, maps):
 
 def make_roofline(B_walk, B_every, footprint, tk, counters, kernel):
     """The roofline object of the bench line: HBM fraction of the algorithmic bytes
-    of the walked work, and the VALU issue fraction from the counters; `bound` is
-    whichever is higher."""
+    of the walked work, the DRAM fraction and VALU issue fraction from the counters.
+    `bound` is the higher of the VALU fraction and the HBM-side fraction, which is
+    the DRAM fraction the counters measured when there is one (the walked-work
+    bytes include sources that the factors sharing them read from L2 and the
+    last-level cache, and can exceed what HBM delivers), else the walked one."""
     t = tk["tile_kernel_ms"] * 1e-3
     hbm = B_walk / t / HBM_PEAK
     valu = None
@@ -954,7 +957,9 @@ def make_roofline(B_walk, B_every, footprint, tk, counters, kernel):
          "l2_hit_rate": counters.get("l2_hit_rate") if counters else None,
          "valu_issue_frac": valu,
          "counters_from": counters.get("source") if counters else None}
-    if valu is not None and valu > hbm:
+    dram = r["dram_frac"]
+    hbm_side = dram if dram is not None else hbm
+    if valu is not None and valu > hbm_side:
         r.update({"bound": "alu", "achieved": counters["valu_insts"] * 64 / t / 1e12, "peak": VALU_PEAK / 1e12,
                   "unit": "TOP/s", "frac": valu,
                   "achieved_is": "VALU lane operations/s (wave64 VALU instructions from the counters x 64 / "

@@ -702,7 +702,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
         double ge = 0.0;
         if constexpr (MODE == kBwd) ge = grad_e[tile.factor];
 
-        int q_head = 0, q_count = 0;   // this wave's hit queue (wave-uniform)
+        // this wave's hit queue (wave-uniform); the head is 0 or 64 (full waves are
+        // drained, and the queue restarts at 0 once a batch's rest is drained), so a
+        // drained wave of entries is head + lane with no wrap
+        int q_head = 0, q_count = 0;
 
         // the first level's probe constants, loaded once per tile (uniform)
         const ProbeLevel pl0(Fp->lv[0]);
@@ -862,7 +865,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         q_count += __popcll(mask);
                         if (q_count >= kChunk) {
                             __builtin_amdgcn_wave_barrier();
-                            drain_hit<PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
+                            drain_hit<PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, q_head + lane);
                             q_head = (q_head + kChunk) & (kQueue - 1);
                             q_count -= kChunk;
                             __builtin_amdgcn_wave_barrier();
@@ -930,7 +933,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         q_count += __popcll(mask);
                         if (q_count >= kChunk) {
                             __builtin_amdgcn_wave_barrier();
-                            drain_hit<PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, (q_head + lane) & (kQueue - 1));
+                            drain_hit<PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, q_head + lane);
                             q_head = (q_head + kChunk) & (kQueue - 1);
                             q_count -= kChunk;
                             __builtin_amdgcn_wave_barrier();
@@ -1142,7 +1145,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         drain_hit<PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, s_q[wave], (q_head + lane) & (kQueue - 1));
                     }
                     __builtin_amdgcn_wave_barrier();
-                    q_head = (q_head + q_count) & (kQueue - 1);
+                    q_head = 0;
                     q_count = 0;
                 }
             }

@@ -38,6 +38,14 @@ def test_roofline_bound_is_the_higher_fraction():
     assert r["bound"] == "alu" and abs(r["frac"] - 0.7) < 1e-12 and r["unit"] == "TOP/s"
     assert abs(r["hbm_frac"] - 0.5) < 1e-12 and abs(r["dram_frac"] - 1e9 / 2e-3 / bench.HBM_PEAK) < 1e-12
     assert r["frac"] <= 1.0
+    # walked-work bytes above peak (shared sources re-read from caches): the counters'
+    # DRAM fraction decides against the VALU fraction
+    r = bench.make_roofline(4 * B, 4 * B, 10, tk, {"valu_insts": valu, "traffic_bytes": 0.4 * bench.HBM_PEAK * 2e-3,
+                                                   "l2_hit_rate": 0.4, "source": "x"}, "k")
+    assert r["hbm_frac"] > 1.0 and r["bound"] == "alu" and abs(r["frac"] - 0.7) < 1e-12
+    r = bench.make_roofline(4 * B, 4 * B, 10, tk, {"valu_insts": valu, "traffic_bytes": 0.9 * bench.HBM_PEAK * 2e-3,
+                                                   "l2_hit_rate": 0.4, "source": "x"}, "k")
+    assert r["bound"] == "hbm"
 
 
 def test_measured_counters_follow_sources_and_launch(tmp_path):

@@ -457,6 +457,11 @@ __device__ __forceinline__ void drain_hit(A& acc, const FactorDesc* __restrict__
 // FP64 mode needs more and runs at what its register count allows.
 template <int PREC, bool KH>
 constexpr int waves_per_eu() { return (PREC == kF64 || KH) ? 1 : 4; }
+// the FP32 kernels are held at exactly four (the scheduler then keeps loads in
+// flight instead of saving registers for a fifth); the others may run up to the
+// eight a SIMD holds, so their scheduler still works for occupancy
+template <int PREC, bool KH>
+constexpr int waves_per_eu_max() { return waves_per_eu<PREC, KH>() == 4 ? 4 : 8; }
 
 // Every point of chunk cg lies in a ball around the anchor and in a box of
 // the source frame, both stored with the chunk.  In the target frame (anchor
@@ -578,7 +583,7 @@ __global__ void k_stage_poses(int64_t F, const double* __restrict__ poses, float
 // point loop is compiled for (1 for single-level batches, whose kernel then
 // holds no state of the other levels; else kMaxLevels).
 template <int MODE, int PREC, int BLOCK, bool KH, bool VAL, int LM>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per_eu<PREC, KH>(), waves_per_eu<PREC, KH>()))) void k_tiles(
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per_eu<PREC, KH>(), waves_per_eu_max<PREC, KH>()))) void k_tiles(
     const FactorDesc* __restrict__ fac, const Tile* __restrict__ tiles, int32_t t_begin, int32_t t_end,
     const double* __restrict__ poses, const float* __restrict__ posef, double* __restrict__ partials,
     uint32_t* __restrict__ counter, const double* __restrict__ grad_e,
@@ -1226,10 +1231,24 @@ __global__ __launch_bounds__(64) void k_reduce(const FactorDesc* __restrict__ fa
     const int k = threadIdx.x;
     if (k < kRow) {
         const int32_t a = tile_first[f], bnd = tile_first[f + 1];
+        // rows are summed in tile order; each step has kStep row loads in flight
+        // before its adds (a factor of a few large sources has hundreds of rows)
+        constexpr int kStep = 16;
         if constexpr (PREC == kN32) {
             float sf = 0.f;
             double si = 0.0;
-            for (int32_t t = a; t < bnd; ++t) {
+            int32_t t = a;
+            for (; t + kStep <= bnd; t += kStep) {
+                double v[kStep];
+#pragma unroll
+                for (int u = 0; u < kStep; ++u) v[u] = partials[(int64_t)(t + u) * kRow + k];
+#pragma unroll
+                for (int u = 0; u < kStep; ++u) {
+                    sf += (float)v[u];
+                    si += v[u];
+                }
+            }
+            for (; t < bnd; ++t) {
                 const double v = partials[(int64_t)t * kRow + k];
                 sf += (float)v;
                 si += v;
@@ -1237,7 +1256,15 @@ __global__ __launch_bounds__(64) void k_reduce(const FactorDesc* __restrict__ fa
             s[k] = (k >= kTerms) ? si : (double)sf;   // counts are exact integers in FP64
         } else {
             double acc = 0.0;
-            for (int32_t t = a; t < bnd; ++t) acc += partials[(int64_t)t * kRow + k];
+            int32_t t = a;
+            for (; t + kStep <= bnd; t += kStep) {
+                double v[kStep];
+#pragma unroll
+                for (int u = 0; u < kStep; ++u) v[u] = partials[(int64_t)(t + u) * kRow + k];
+#pragma unroll
+                for (int u = 0; u < kStep; ++u) acc += v[u];
+            }
+            for (; t < bnd; ++t) acc += partials[(int64_t)t * kRow + k];
             s[k] = acc;
         }
     }

@@ -87,6 +87,9 @@ __device__ __forceinline__ uint32_t bfi_low(uint32_t a, uint32_t b) {
 // lookup (load factor <= 1/4): it is either the block, or empty, or (rarely)
 // another block, and only then is the chain walked.  The occupancy test and the
 // popcount below the voxel's bit work on the 64-bit mask as a whole.
+// PRIO: the caller raised the wave's issue priority for the probe; it is
+// lowered once the first table load is issued, while the wave waits for it.
+template <bool PRIO = false>
 __device__ __forceinline__ int32_t lookup_u(const uint64_t* __restrict__ slots, uint32_t log2cap, uint32_t ux,
                                             uint32_t uy, uint32_t uz) {
     const uint32_t bx = ux >> kBlockShift, by = uy >> kBlockShift, bz = uz >> kBlockShift;
@@ -94,6 +97,7 @@ __device__ __forceinline__ int32_t lookup_u(const uint64_t* __restrict__ slots, 
     const uint64_t bk = ((uint64_t)khi << 32) | klo;
     uint32_t h = slot_of_words(klo, khi, log2cap);
     u64x2 e = load_off<u64x2>(slots, h << 4);
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
     bool same = (e.x >> kBaseBits) == bk;
     if (!same && e.x != kEmpty) {
         // another block in the first slot: walk the chain (linear probing)

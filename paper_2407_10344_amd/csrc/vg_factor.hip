@@ -880,6 +880,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 } else if constexpr (CMP) {
                     // ---- probe every point, queue its hits, drain full waves of hits
                     HitQueue& Q = s_q[wave];
+                    // issue priority up while the chunk's keys are formed and its table
+                    // loads issued (lowered in the lookup once they are out)
+                    if constexpr (SC) __builtin_amdgcn_s_setprio(1);
                     const float dx = cur.x[0], dy = cur.x[1], dz = cur.x[2];
                     float yl[3];
 #pragma unroll
@@ -920,7 +923,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                             nlook = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in));
                         }
                         prb2[l >> 1] += nlook << (16 * (l & 1));
-                        if (in) v = lookup_u(pl.slots, pl.log2cap, ku[0], ku[1], ku[2]);
+                        if (in) v = lookup_u<SC>(pl.slots, pl.log2cap, ku[0], ku[1], ku[2]);
+                        if constexpr (SC) __builtin_amdgcn_s_setprio(0);   // no lane looked up
                         const bool hit = v >= 0;
                         const uint64_t mask = __builtin_amdgcn_ballot_w64(hit);
                         inl2[l >> 1] += (uint32_t)__popcll(mask) << (16 * (l & 1));

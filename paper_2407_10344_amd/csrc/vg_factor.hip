@@ -1489,7 +1489,11 @@ vg_status launch_tiles(vg_batch* b, const Workspace& ws, int mode, const double*
                        int64_t f1) {
     if (grid < 1) grid = 1;
     if (t1 <= t0) return VG_OK;
-    if (b->opt.precision != kF64 && f1 > f0) {
+    // FP32 pose copies for the FP32 kernels; the one-level compensated
+    // linearization forms its rotation from the FP64 poses and reads none
+    const bool one_level_lin = mode == kLin && b->opt.precision == kC32 && !b->opt.lane_kahan &&
+                               !b->opt.surface_validation && b->L == 1;
+    if (b->opt.precision != kF64 && f1 > f0 && !one_level_lin) {
         const int64_t nf = (f1 - f0) * 16;
         k_stage_poses<<<(int)((nf + 255) / 256), 256, 0, b->ctx->stream>>>(f1 - f0, d_poses + 12 * f0,
                                                                           ws.posef + 16 * f0);

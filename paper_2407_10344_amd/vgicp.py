@@ -280,10 +280,17 @@ class FactorBatch:
         check(load().vg_overlap(self.handle, _p(P), _p(o)))
         return o
 
-    def linearize_async(self, d_poses: torch.Tensor):
+    def linearize_async(self, d_poses: torch.Tensor, out: torch.Tensor = None, inliers: torch.Tensor = None):
+        """e/H/b rows (F x 43 FP64) and inlier counts (F x L int64) on the device,
+        stream-ordered; out / inliers: caller tensors to reuse (else new ones)."""
         d_poses = d_poses.contiguous()
-        out = torch.empty((self.F, 43), dtype=torch.float64, device=d_poses.device)
-        inl = torch.empty((self.F, self.L), dtype=torch.int64, device=d_poses.device)
+        if out is None:
+            out = torch.empty((self.F, 43), dtype=torch.float64, device=d_poses.device)
+        if inliers is None:
+            inliers = torch.empty((self.F, self.L), dtype=torch.int64, device=d_poses.device)
+        assert out.is_contiguous() and out.dtype == torch.float64 and out.shape == (self.F, 43)
+        assert inliers.is_contiguous() and inliers.dtype == torch.int64 and inliers.shape == (self.F, self.L)
+        inl = inliers
         self.ctx.enter()
         check(load().vg_linearize_async(self.handle, _tp(d_poses), _tp(out), _tp(inl)))
         self.ctx.leave()

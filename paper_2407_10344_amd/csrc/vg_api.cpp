@@ -1454,7 +1454,9 @@ extern "C" vg_status vg_batch_tune(vg_batch* b, const double* poses, int32_t rep
     // candidates in order of preference: a later candidate replaces an earlier one
     // only when it is faster by more than 1.5 %, so timing noise does not flip the choice
     const int orders[] = {1, 2};
-    const int tiles[] = {8192, 16384, 32768, 4096, 2048, 1024, 512, 256};
+    // preference order: larger tiles first (fewer partial rows to reduce, fewer
+    // counter atomics); a later shape replaces the incumbent only if 1.5 % faster
+    const int tiles[] = {16384, 8192, 32768, 4096, 2048, 1024, 512, 256};
     const int blocks[] = {256, 128, 512};
     const int occ[] = {2, 1, 4};   // multiples of the full-occupancy workgroup count
     float best = 1e30f;

@@ -812,8 +812,13 @@ def main():
         log("autotuned %s in %.1f s" % (chosen, time.time() - t))
 
     if args.profile_steps:
+        # the steps as the bench times them: device-resident poses and results,
+        # launched back to back, one synchronization at the end
+        d_poses = torch.tensor(np.ascontiguousarray(poses), dtype=torch.float64, device="cuda")
+        out = torch.empty((batch.F, 43), dtype=torch.float64, device="cuda")
+        inl_d = torch.empty((batch.F, batch.L), dtype=torch.int64, device="cuda")
         for _ in range(args.warmup + args.profile_steps):
-            batch.linearize(poses)
+            batch.linearize_async(d_poses, out, inl_d)
         torch.cuda.synchronize()
         # kernels of known traffic, to scale the memory counters: a fill that
         # writes COPY_BYTES, a reduction that streams them, and a gather of

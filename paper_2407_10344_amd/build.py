@@ -26,6 +26,7 @@ SOURCES = ["vg_api.cpp", "vg_voxelmap.hip", "vg_factor.hip", "vg_lm.hip", "vg_gr
 SOURCE_FLAGS = {"vg_preprocess.hip": ["-ffp-contract=off"]}
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 FLAGS = [
     "-O3",
@@ -64,7 +65,9 @@ def build(verbose: bool = False, extra=(), out: str = OUT) -> str:
     with ThreadPoolExecutor(len(SOURCES)) as ex:
         objs = list(ex.map(lambda s: _compile(s, extra), SOURCES))
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs]
+    # roctx: the named ranges around the library's calls (rocprofv3 --marker-trace)
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs,
+           "-L" + os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr[-8000:])

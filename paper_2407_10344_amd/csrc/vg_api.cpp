@@ -13,6 +13,7 @@
 #include <sstream>
 
 #include "vg_internal.h"
+#include "vg_timeline.h"
 
 // Device scratch of the allocation-free linearization (vg_linearize_noalloc):
 // tile counters, staged FP32 poses and tile partial rows.  Every device the
@@ -267,6 +268,7 @@ static vg_status check_resolutions(const double* resolutions, int32_t L) {
 extern "C" vg_status vg_build_voxelmap(vg_context* ctx, const double* xyz, const double* cov, int64_t n,
                                        const double* resolutions, int32_t L, vg_voxelmap** out) {
     g_err.clear();
+    const TimelineRange range_("vg_build_voxelmap");
     if (!ctx_ok(ctx)) return state_err("invalid context");
     if (out == nullptr) return invalid("out is NULL");
     *out = nullptr;
@@ -415,6 +417,7 @@ static vg_status make_source(vg_context* ctx, const double* d_xyz, const double*
 extern "C" vg_status vg_create_source(vg_context* ctx, const double* xyz, const double* cov, const double* normals,
                                       int64_t n, vg_source** out) {
     g_err.clear();
+    const TimelineRange range_("vg_create_source");
     if (!ctx_ok(ctx)) return state_err("invalid context");
     if (out == nullptr) return invalid("out is NULL");
     *out = nullptr;
@@ -458,6 +461,7 @@ extern "C" vg_status vg_create_source(vg_context* ctx, const double* xyz, const 
 
 extern "C" vg_status vg_source_set_points_async(vg_source* src, const void* d_xyz, int32_t dtype) {
     g_err.clear();
+    const TimelineRange range_("vg_source_set_points_async");
     if (!src_ok(src)) return state_err("invalid source");
     if (dtype != 0 && dtype != 1) return invalid("dtype must be 0 (float32) or 1 (float64)");
     if (src->n > 0 && d_xyz == nullptr) return invalid("d_xyz is NULL");
@@ -485,6 +489,7 @@ static bool cloud_ok(const vg_cloud* c) { return c != nullptr && c->magic == kCl
 extern "C" vg_status vg_preprocess(vg_context* ctx, const double* xyz, int64_t n, double r, int32_t k,
                                    const double* sensor, vg_cloud** out) {
     g_err.clear();
+    const TimelineRange range_("vg_preprocess");
     if (!ctx_ok(ctx)) return state_err("invalid context");
     if (out == nullptr) return invalid("out is NULL");
     *out = nullptr;
@@ -557,6 +562,7 @@ extern "C" vg_status vg_cloud_export(const vg_cloud* cloud, double* xyz, double*
 
 extern "C" vg_status vg_create_source_from_cloud(vg_context* ctx, const vg_cloud* cloud, vg_source** out) {
     g_err.clear();
+    const TimelineRange range_("vg_create_source_from_cloud");
     if (!ctx_ok(ctx)) return state_err("invalid context");
     if (!cloud_ok(cloud)) return state_err("invalid cloud");
     if (cloud->ctx != ctx) return state_err("cloud from another context");
@@ -570,6 +576,7 @@ extern "C" vg_status vg_create_source_from_cloud(vg_context* ctx, const vg_cloud
 extern "C" vg_status vg_build_voxelmap_from_cloud(vg_context* ctx, const vg_cloud* cloud, const double* resolutions,
                                                   int32_t L, vg_voxelmap** out) {
     g_err.clear();
+    const TimelineRange range_("vg_build_voxelmap_from_cloud");
     if (!ctx_ok(ctx)) return state_err("invalid context");
     if (!cloud_ok(cloud)) return state_err("invalid cloud");
     if (cloud->ctx != ctx) return state_err("cloud from another context");
@@ -855,6 +862,7 @@ extern "C" vg_status vg_create_factor_batch(vg_context* ctx, int64_t F, vg_sourc
                                             vg_voxelmap* const* tgt, const double* target_viewpoints,
                                             const vg_batch_options* opts, vg_batch** out) {
     g_err.clear();
+    const TimelineRange range_("vg_create_factor_batch");
     if (!ctx_ok(ctx)) return state_err("invalid context");
     if (out == nullptr) return invalid("out is NULL");
     *out = nullptr;
@@ -1050,6 +1058,7 @@ extern "C" vg_status vg_batch_destroy(vg_batch* b) {
 extern "C" vg_status vg_linearize(vg_batch* b, const double* poses, double* e, double* H, double* bv,
                                   int64_t* inliers) {
     g_err.clear();
+    const TimelineRange range_("vg_linearize");
     if (!bat_ok(b)) return state_err("invalid batch");
     if (e == nullptr || H == nullptr || bv == nullptr) return invalid("e, H or b is NULL");
     VG_TRY(check_poses(poses, b->F));
@@ -1068,6 +1077,7 @@ extern "C" vg_status vg_linearize(vg_batch* b, const double* poses, double* e, d
 
 extern "C" vg_status vg_evaluate(vg_batch* b, const double* poses, double* e) {
     g_err.clear();
+    const TimelineRange range_("vg_evaluate");
     if (!bat_ok(b)) return state_err("invalid batch");
     if (e == nullptr) return invalid("e is NULL");
     VG_TRY(check_poses(poses, b->F));
@@ -1084,6 +1094,7 @@ extern "C" vg_status vg_evaluate(vg_batch* b, const double* poses, double* e) {
 
 extern "C" vg_status vg_overlap(vg_batch* b, const double* poses, double* overlap) {
     g_err.clear();
+    const TimelineRange range_("vg_overlap");
     if (!bat_ok(b)) return state_err("invalid batch");
     if (overlap == nullptr) return invalid("overlap is NULL");
     VG_TRY(check_poses(poses, b->F));
@@ -1104,6 +1115,7 @@ extern "C" vg_status vg_overlap(vg_batch* b, const double* poses, double* overla
 
 extern "C" vg_status vg_linearize_async(vg_batch* b, const double* d_poses, double* d_out, int64_t* d_inliers) {
     g_err.clear();
+    const TimelineRange range_("vg_linearize_async");
     if (!bat_ok(b)) return state_err("invalid batch");
     if (d_poses == nullptr || d_out == nullptr) return invalid("d_poses or d_out is NULL");
     VG_HIP(hipSetDevice(b->ctx->device));
@@ -1112,6 +1124,7 @@ extern "C" vg_status vg_linearize_async(vg_batch* b, const double* d_poses, doub
 
 extern "C" vg_status vg_linearize_noalloc(vg_batch* b, const double* d_poses, double* d_out, int64_t* d_inliers) {
     g_err.clear();
+    const TimelineRange range_("vg_linearize_noalloc");
     if (!bat_ok(b)) return state_err("invalid batch");
     if (d_poses == nullptr || d_out == nullptr) return invalid("d_poses or d_out is NULL");
     VG_HIP(hipSetDevice(b->ctx->device));
@@ -1145,6 +1158,7 @@ extern "C" vg_status vg_linearize_noalloc(vg_batch* b, const double* d_poses, do
 
 extern "C" vg_status vg_evaluate_async(vg_batch* b, const double* d_poses, double* d_e) {
     g_err.clear();
+    const TimelineRange range_("vg_evaluate_async");
     if (!bat_ok(b)) return state_err("invalid batch");
     if (d_poses == nullptr || d_e == nullptr) return invalid("d_poses or d_e is NULL");
     VG_HIP(hipSetDevice(b->ctx->device));
@@ -1154,6 +1168,7 @@ extern "C" vg_status vg_evaluate_async(vg_batch* b, const double* d_poses, doubl
 extern "C" vg_status vg_backward_async(vg_batch* b, const double* d_poses, const double* d_grad_e, const double* d_jr,
                                        double* d_grad_xi, void* d_grad_points, int32_t points_dtype) {
     g_err.clear();
+    const TimelineRange range_("vg_backward_async");
     if (!bat_ok(b)) return state_err("invalid batch");
     if (d_poses == nullptr || d_grad_e == nullptr || d_grad_xi == nullptr)
         return invalid("d_poses, d_grad_e or d_grad_xi is NULL");
@@ -1185,6 +1200,7 @@ extern "C" vg_status vg_backward_async(vg_batch* b, const double* d_poses, const
 extern "C" vg_status vg_se3_retract_async(vg_context* ctx, int64_t F, const double* d_T0, const double* d_xi,
                                           double* d_T, double* d_jr) {
     g_err.clear();
+    const TimelineRange range_("vg_se3_retract_async");
     if (!ctx_ok(ctx)) return state_err("invalid context");
     if (F < 0) return invalid("F < 0");
     if (F > 0 && (d_T0 == nullptr || d_xi == nullptr || d_T == nullptr)) return invalid("NULL pointer");
@@ -1215,6 +1231,7 @@ vg_status lm_step(vg_batch* b, double* d_poses, double* d_lambda, double* d_e, i
 extern "C" vg_status vg_lm_step_async(vg_batch* b, double* d_poses, double* d_lambda, double* d_e,
                                       int32_t* d_accepted) {
     g_err.clear();
+    const TimelineRange range_("vg_lm_step_async");
     if (!bat_ok(b)) return state_err("invalid batch");
     if (d_poses == nullptr || d_lambda == nullptr) return invalid("d_poses or d_lambda is NULL");
     VG_HIP(hipSetDevice(b->ctx->device));
@@ -1224,6 +1241,7 @@ extern "C" vg_status vg_lm_step_async(vg_batch* b, double* d_poses, double* d_la
 extern "C" vg_status vg_lm_run(vg_batch* b, const double* poses_in, int32_t iters, double lambda0, double* poses_out,
                                int32_t* accepted, double* e_hist) {
     g_err.clear();
+    const TimelineRange range_("vg_lm_run");
     if (!bat_ok(b)) return state_err("invalid batch");
     if (poses_out == nullptr) return invalid("poses_out is NULL");
     if (iters < 0 || iters > 10000) return invalid("iters out of range");
@@ -1292,6 +1310,7 @@ extern "C" vg_status vg_batch_work(vg_batch* b, int64_t* walked_points, int64_t*
 extern "C" vg_status vg_correspondences(vg_batch* b, const double* pose, int64_t factor, int64_t* keys,
                                         int32_t* found) {
     g_err.clear();
+    const TimelineRange range_("vg_correspondences");
     if (!bat_ok(b)) return state_err("invalid batch");
     if (factor < 0 || factor >= b->F) return invalid("factor out of range");
     if (keys == nullptr || found == nullptr) return invalid("keys or found is NULL");
@@ -1385,6 +1404,7 @@ extern "C" vg_status vg_batch_time_kernels(vg_batch* b, const double* poses, int
 
 extern "C" vg_status vg_batch_tune(vg_batch* b, const double* poses, int32_t reps, int32_t* chosen) {
     g_err.clear();
+    const TimelineRange range_("vg_batch_tune");
     if (!bat_ok(b)) return state_err("invalid batch");
     if (reps < 1 || reps > 1000) return invalid("reps out of range");
     VG_TRY(check_poses(poses, b->F));

@@ -14,6 +14,7 @@
 #include <map>
 
 #include "vg_device.h"
+#include "vg_timeline.h"
 
 struct vg_graph {
     vg_context* ctx = nullptr;
@@ -213,6 +214,7 @@ extern "C" vg_status vg_graph_structure(const vg_graph* g, int64_t* nnz_blocks, 
 
 extern "C" vg_status vg_graph_assemble_async(vg_graph* g, const double* d_poses, const double* d_lin,
                                              double* d_values, double* d_rhs) {
+    const vg::TimelineRange range_("vg_graph_assemble_async");
     set_error("");
     if (!graph_ok(g)) {
         set_error("invalid graph");

@@ -72,3 +72,16 @@ def test_context_without_device_fails_cleanly(lib):
     assert out.value is None
     assert len(lib.vg_last_error()) > 0
     assert lib.vg_context_create(0, None, None) == -1
+
+
+def test_library_marks_its_calls_for_profilers():
+    """The library's calls open named roctx ranges (shown by rocprofv3
+    --marker-trace): it imports the range calls from the roctx library."""
+    import shutil
+    import subprocess
+    from paper_2407_10344_amd import _lib
+    nm = shutil.which("nm")
+    if nm is None or not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("nm or the built library missing")
+    out = subprocess.run([nm, "-D", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    assert "roctxRangePushA" in out and "roctxRangePop" in out

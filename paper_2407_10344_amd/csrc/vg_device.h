@@ -83,45 +83,60 @@ __device__ __forceinline__ uint32_t bfi_low(uint32_t a, uint32_t b) {
 }
 
 // Record index of the voxel with biased key (ux, uy, uz) = relative key + 8192
-// (each in [0, 16383]), or -1.  The first table entry decides almost every
-// lookup (load factor <= 1/4): it is either the block, or empty, or (rarely)
-// another block, and only then is the chain walked.  The occupancy test and the
-// popcount below the voxel's bit work on the 64-bit mask as a whole.
-// PRIO: the caller raised the wave's issue priority for the probe; it is
-// lowered once the first table load is issued, while the wave waits for it.
-template <bool PRIO = false>
-__device__ __forceinline__ int32_t lookup_u(const uint64_t* __restrict__ slots, uint32_t log2cap, uint32_t ux,
-                                            uint32_t uy, uint32_t uz) {
+// (each in [0, 16383]), or -1, in two halves so a caller can do other work
+// while the first table load is in flight: lookup_issue forms the block key,
+// slot and bit and issues the load; lookup_finish takes the result.  The first
+// table entry decides almost every lookup (load factor <= 1/4): it is either
+// the block, or empty, or (rarely) another block, and only then is the chain
+// walked.  The occupancy test and the popcount below the voxel's bit work on
+// the 64-bit mask as a whole.
+struct BlockProbe {
+    u64x2 e;           // the table entry (first slot until the chain is walked)
+    uint64_t bk;       // block key
+    uint32_t h;        // slot
+    uint32_t nlocal;   // 63 - bit of the voxel in its block's mask (in bits 0..5)
+};
+__device__ __forceinline__ void lookup_issue(const uint64_t* __restrict__ slots, uint32_t log2cap, uint32_t ux,
+                                             uint32_t uy, uint32_t uz, BlockProbe& p) {
     const uint32_t bx = ux >> kBlockShift, by = uy >> kBlockShift, bz = uz >> kBlockShift;
     const uint32_t klo = (bx << (2 * kBlockBits)) | (by << kBlockBits) | bz, khi = bx >> (32 - 2 * kBlockBits);
-    const uint64_t bk = ((uint64_t)khi << 32) | klo;
-    uint32_t h = slot_of_words(klo, khi, log2cap);
-    u64x2 e = load_off<u64x2>(slots, h << 4);
-    if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
-    bool same = (e.x >> kBaseBits) == bk;
-    if (!same && e.x != kEmpty) {
+    p.bk = ((uint64_t)khi << 32) | klo;
+    p.h = slot_of_words(klo, khi, log2cap);
+    p.e = load_off<u64x2>(slots, p.h << 4);
+    // bit of the voxel in the mask: x + 4 y + 16 z of its position in the block
+    // (two bit-field inserts), complemented in bits 0..5; the bits above are
+    // left over from z, and the 64-bit shift below reads only bits 0..5
+    p.nlocal = bfi_low<15u>(bfi_low<3u>(ux, uy << 2), uz << 4) ^ 63u;
+}
+__device__ __forceinline__ int32_t lookup_finish(const uint64_t* __restrict__ slots, uint32_t log2cap,
+                                                 BlockProbe& p) {
+    bool same = (p.e.x >> kBaseBits) == p.bk;
+    if (!same && p.e.x != kEmpty) {
         // another block in the first slot: walk the chain (linear probing)
         const uint32_t mask = (1u << log2cap) - 1u;
+        uint32_t h = p.h;
         for (uint32_t it = 0; it < mask; ++it) {
             h = (h + 1u) & mask;
-            e = load_off<u64x2>(slots, h << 4);
-            same = (e.x >> kBaseBits) == bk;
-            if (same || e.x == kEmpty) break;
+            p.e = load_off<u64x2>(slots, h << 4);
+            same = (p.e.x >> kBaseBits) == p.bk;
+            if (same || p.e.x == kEmpty) break;
         }
     }
-    // an empty entry never holds the block (a valid entry word is never all ones)
-    // bit of the voxel in the mask: x + 4 y + 16 z of its position in the block
-    // (two bit-field inserts; bits above 5 are left over from z, and the 64-bit
-    // shifts below read only bits 0..5 of their shift operand)
-    const uint32_t local = bfi_low<15u>(bfi_low<3u>(ux, uy << 2), uz << 4) & 63u;
-    const uint64_t m = e.y;
-    const bool occupied = ((m >> local) & 1ull) != 0ull;
-    // record = first record of the block + occupied voxels below this one
-    const uint64_t below = m & ~(~0ull << local);
-    uint32_t rec = (uint32_t)e.x & (uint32_t)kBaseMask;
-    rec += (uint32_t)__popc((uint32_t)below);
-    rec += (uint32_t)__popc((uint32_t)(below >> 32));
-    return (same && e.x != kEmpty && occupied) ? (int32_t)rec : -1;
+    // the mask shifted left by 63 - bit: the voxel's bit becomes the sign bit,
+    // and the bits left are those at and below it, so their count is the
+    // voxel's rank among the block's occupied voxels plus one.  An empty entry
+    // never holds the block (a valid entry word is never all ones).
+    const uint64_t t = p.e.y << (p.nlocal & 63u);
+    const bool occupied = (int32_t)(uint32_t)(t >> 32) < 0;
+    const uint32_t cnt = ((uint32_t)p.e.x & (uint32_t)kBaseMask) + (uint32_t)__popc((uint32_t)t) +
+                         (uint32_t)__popc((uint32_t)(t >> 32));
+    return (same && p.e.x != kEmpty && occupied) ? (int32_t)(cnt - 1u) : -1;
+}
+__device__ __forceinline__ int32_t lookup_u(const uint64_t* __restrict__ slots, uint32_t log2cap, uint32_t ux,
+                                            uint32_t uy, uint32_t uz) {
+    BlockProbe p;
+    lookup_issue(slots, log2cap, ux, uy, uz, p);
+    return lookup_finish(slots, log2cap, p);
 }
 
 // The same for a relative key (kx, ky, kz) (each in [-8192, 8191]).

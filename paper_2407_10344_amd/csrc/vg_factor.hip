@@ -232,8 +232,8 @@ struct TileShared {
 // probe (keys, bounding box, block-table lookup) runs on every point, the
 // expensive part (record gather, fused covariance and its inverse, residual,
 // 28 terms) only on full waves of hits.  Ring of 128 entries: a push adds at
-// most 64 (one level of one chunk) and a full wave of 64 is drained as soon as
-// 64 are queued, so at most 127 are ever held.  The FP64 mode leaves x, y, z
+// most 64 (one level of one chunk) and once 64 are queued a full wave is
+// drained before the next push, so at most 127 are ever held.  The FP64 mode leaves x, y, z
 // unused (its drain re-reads the FP64 position).
 constexpr int kQueue = 128;
 static_assert(kMaxTilePoints < 65536, "per-tile counts are packed in 16 bits");
@@ -605,6 +605,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
     // one-level compacted linearization: positions in voxel units (the rotation
     // and the anchor remainders scaled by 1/r), so keys need no multiply
     constexpr bool SC = CMP && PREC == kC32 && LM == 1;
+    // the compacted probes issue a chunk's table loads and drain a full wave of
+    // earlier hits while they are in flight, then push the chunk's hits; the
+    // compensated kernel with validation (short of registers for it) drains
+    // after the push instead.  Either way a drain takes the queue's oldest 64
+    // entries, so both orders process the same hits in the same lanes.
+    constexpr bool DRAIN_EARLY = !(PREC == kC32 && VAL);
     __shared__ TileShared sh;
     using QueueT = typename std::conditional<CMP, HitQueue, int32_t>::type;
     __shared__ QueueT s_q[CMP ? NW : 1];
@@ -714,6 +720,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
 
         // the first level's probe constants, loaded once per tile (uniform)
         const ProbeLevel pl0(Fp->lv[0]);
+        // one full wave of queued hits, the oldest 64 (head + lane, no wrap)
+        auto drain_full = [&](const QueueT& Q) {
+            if constexpr (CMP) {
+                if (q_count >= kChunk) {
+                    __builtin_amdgcn_wave_barrier();
+                    drain_hit<PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, q_head + lane);
+                    q_head = (q_head + kChunk) & (kQueue - 1);
+                    q_count -= kChunk;
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+        };
         // the source's positions as a buffer (3 x n_pad floats; sources hold fewer than 2^27 points)
         const __amdgpu_buffer_rsrc_t xr = raw_rsrc(Fp->dxyz, (uint32_t)(3 * n_pad * (int64_t)sizeof(float)));
         const int32_t n32 = (int32_t)n;
@@ -855,7 +873,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                         }
                         int32_t v = -1;
                         prb2[l >> 1] += (uint32_t)__popcll(__ballot(in)) << (16 * (l & 1));
-                        if (in) v = lookup(lv.slots, lv.log2cap, kq[0], kq[1], kq[2]);
+                        // a full wave of earlier hits is processed while the table loads
+                        // are in flight (see the compensated path below)
+                        BlockProbe bp;
+                        if (in)
+                            lookup_issue(lv.slots, lv.log2cap, (uint32_t)(kq[0] + kKeyBias), (uint32_t)(kq[1] + kKeyBias),
+                                         (uint32_t)(kq[2] + kKeyBias), bp);
+                        if constexpr (DRAIN_EARLY) drain_full(Q);
+                        if (in) v = lookup_finish(lv.slots, lv.log2cap, bp);
                         const bool hit = v >= 0;
                         const uint64_t mask = __ballot(hit);
                         inl2[l >> 1] += (uint32_t)__popcll(mask) << (16 * (l & 1));
@@ -868,20 +893,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                             Q.cl[e] = (c << 2) | l;
                         }
                         q_count += __popcll(mask);
-                        if (q_count >= kChunk) {
-                            __builtin_amdgcn_wave_barrier();
-                            drain_hit<PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, q_head + lane);
-                            q_head = (q_head + kChunk) & (kQueue - 1);
-                            q_count -= kChunk;
-                            __builtin_amdgcn_wave_barrier();
-                        }
+                        if constexpr (!DRAIN_EARLY) drain_full(Q);
                     }
                     continue;
                 } else if constexpr (CMP) {
                     // ---- probe every point, queue its hits, drain full waves of hits
                     HitQueue& Q = s_q[wave];
                     // issue priority up while the chunk's keys are formed and its table
-                    // loads issued (lowered in the lookup once they are out)
+                    // loads issued (lowered once they are out)
                     if constexpr (SC) __builtin_amdgcn_s_setprio(1);
                     const float dx = cur.x[0], dy = cur.x[1], dz = cur.x[2];
                     float yl[3];
@@ -923,8 +942,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                             nlook = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(in));
                         }
                         prb2[l >> 1] += nlook << (16 * (l & 1));
-                        if (in) v = lookup_u<SC>(pl.slots, pl.log2cap, ku[0], ku[1], ku[2]);
-                        if constexpr (SC) __builtin_amdgcn_s_setprio(0);   // no lane looked up
+                        // the table loads are issued (and the priority lowered), then a
+                        // full wave of earlier hits is processed while they are in flight
+                        // (the queue is FIFO and a drain takes its oldest 64 entries, so
+                        // every drain sees the same hits in the same lanes as draining
+                        // after the push would)
+                        BlockProbe bp;
+                        if (in) lookup_issue(pl.slots, pl.log2cap, ku[0], ku[1], ku[2], bp);
+                        if constexpr (SC) __builtin_amdgcn_s_setprio(0);
+                        if constexpr (DRAIN_EARLY) drain_full(Q);
+                        if (in) v = lookup_finish(pl.slots, pl.log2cap, bp);
                         const bool hit = v >= 0;
                         const uint64_t mask = __builtin_amdgcn_ballot_w64(hit);
                         inl2[l >> 1] += (uint32_t)__popcll(mask) << (16 * (l & 1));
@@ -940,13 +967,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                             Q.cl[e] = SC ? c * (int)sizeof(ChunkLds) : (c << 2) | l;
                         }
                         q_count += __popcll(mask);
-                        if (q_count >= kChunk) {
-                            __builtin_amdgcn_wave_barrier();
-                            drain_hit<PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, q_head + lane);
-                            q_head = (q_head + kChunk) & (kQueue - 1);
-                            q_count -= kChunk;
-                            __builtin_amdgcn_wave_barrier();
-                        }
+                        if constexpr (!DRAIN_EARLY) drain_full(Q);
                     }
                     continue;
                 }
@@ -1147,7 +1168,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 }
             }
             if constexpr (CMP) {
-                // the last, partial wave of queued hits (they refer to this batch's chunks)
+                // the queued hits refer to this batch's chunks: a full wave left by a
+                // probe that drains before pushing, then the partial rest
+                drain_full(s_q[wave]);
                 if (q_count > 0) {
                     __builtin_amdgcn_wave_barrier();
                     if (lane < q_count) {

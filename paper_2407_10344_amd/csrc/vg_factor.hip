@@ -145,6 +145,22 @@ __device__ __forceinline__ double wave_sum_transposed(double (&v)[32], int lane)
 
 // Gauss-Newton terms of one (point, voxel) pair in the target orientation.
 template <typename T, typename A>
+__device__ __forceinline__ void add_lin_terms(A& acc, const T d[3], const T w[6], const T z[3]);
+
+// What one queued hit adds: the 28 terms when linearizing, d^T W d when
+// evaluating (z is then unused).
+template <int MODE, typename T, typename A>
+__device__ __forceinline__ void add_hit(A& acc, const T d[3], const T w[6], const T z[3]) {
+    if constexpr (MODE == kLin) {
+        add_lin_terms(acc, d, w, z);
+    } else {
+        T u[3];
+        sym3_mul(w, d, u);
+        acc.add(0, d[0] * u[0] + d[1] * u[1] + d[2] * u[2]);
+    }
+}
+
+template <typename T, typename A>
 __device__ __forceinline__ void add_lin_terms(A& acc, const T d[3], const T w[6], const T z[3]) {
     T u[3];
     sym3_mul(w, d, u);
@@ -228,10 +244,10 @@ struct TileShared {
     uint8_t reach[kMaxTileChunks];     // kChunkCulled / kChunkStraddles / kChunkInside
 };
 
-// Per-wave queue of (point, level) hits of the compacted linearization: the
-// probe (keys, bounding box, block-table lookup) runs on every point, the
-// expensive part (record gather, fused covariance and its inverse, residual,
-// 28 terms) only on full waves of hits.  Ring of 128 entries: a push adds at
+// Per-wave queue of (point, level) hits of the compacted linearization and
+// evaluation: the probe (keys, bounding box, block-table lookup) runs on every
+// point, the expensive part (record gather, fused covariance and its inverse,
+// residual, the 28 terms or e) only on full waves of hits.  Ring of 128 entries: a push adds at
 // most 64 (one level of one chunk) and once 64 are queued a full wave is
 // drained before the next push, so at most 127 are ever held.  The FP64 mode leaves x, y, z
 // unused (its drain re-reads the FP64 position).
@@ -310,7 +326,7 @@ __device__ __forceinline__ void point_S(const FactorDesc* __restrict__ Fp, int64
 // chunk array.  The fused covariance is formed with the voxel's covariance
 // added inside the rotation's last multiply-adds, and the residual as one FMA
 // chain starting from the voxel centre.
-template <bool SC, typename A>
+template <int MODE, bool SC, typename A>
 __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restrict__ Fp, const TileShared& sh,
                                               const ProbeLevel& pl0, const double* P, const float* R, int64_t n_pad,
                                               float dx, float dy, float dz, int32_t i, int32_t v, int32_t cl) {
@@ -364,7 +380,7 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
             const double base = fma(-(double)jk[a], pl0.r64, fhv[a]) - (double)mv[a];
             d[a] = -(float)fma(P[3 * a + 2], ddz, fma(P[3 * a + 1], ddy, fma(P[3 * a], ddx, base)));
         }
-        add_lin_terms(acc, d, W, z);
+        add_hit<MODE>(acc, d, W, z);
         return;
     }
     const int c = cl >> 2, l = cl & 3;
@@ -413,13 +429,13 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
         const double t = fma(P[3 * a + 2], ddz, fma(P[3 * a + 1], ddy, fma(P[3 * a], ddx, sh.frac[3 * c + a] - half)));
         d[a] = (float)((double)mv[a] - fma(-(double)jk[a], r64, t));
     }
-    add_lin_terms(acc, d, W, z);
+    add_hit<MODE>(acc, d, W, z);
 }
 
 // Terms of one queued hit in the FP64 mode: the point is re-read from the
 // FP64 positions (it was read one drain ago, so the load hits the caches) and
 // the arithmetic is the uncompacted FP64 path's.
-template <typename A>
+template <int MODE, typename A>
 __device__ __forceinline__ void cmp_hit_terms64(A& acc, const FactorDesc* __restrict__ Fp, const double* P,
                                                 const double* R, const double* tt, int64_t n_pad, int32_t i,
                                                 int32_t v, int32_t cl) {
@@ -439,18 +455,18 @@ __device__ __forceinline__ void cmp_hit_terms64(A& acc, const FactorDesc* __rest
     const double M[6] = {q1.y + S[0], q2.x + S[1], q2.y + S[2], q3.x + S[3], q3.y + S[4], q4.x + S[5]};
     double W[6];
     sym3_inverse(M, W);
-    add_lin_terms(acc, d, W, z);
+    add_hit<MODE>(acc, d, W, z);
 }
 
 // One queued hit, by precision mode.
-template <int PREC, bool SC, typename A, typename T>
+template <int MODE, int PREC, bool SC, typename A, typename T>
 __device__ __forceinline__ void drain_hit(A& acc, const FactorDesc* __restrict__ Fp, const TileShared& sh,
                                           const ProbeLevel& pl0, const double* P, const T* R, const T* tt,
                                           int64_t n_pad, const HitQueue& Q, int e) {
     if constexpr (PREC == kC32)
-        cmp_hit_terms<SC>(acc, Fp, sh, pl0, P, R, n_pad, Q.x[e], Q.y[e], Q.z[e], Q.pt[e], Q.rec[e], Q.cl[e]);
+        cmp_hit_terms<MODE, SC>(acc, Fp, sh, pl0, P, R, n_pad, Q.x[e], Q.y[e], Q.z[e], Q.pt[e], Q.rec[e], Q.cl[e]);
     else
-        cmp_hit_terms64(acc, Fp, P, R, tt, n_pad, Q.pt[e], Q.rec[e], Q.cl[e]);
+        cmp_hit_terms64<MODE>(acc, Fp, P, R, tt, n_pad, Q.pt[e], Q.rec[e], Q.cl[e]);
 }
 
 // Register budget: 4 waves per SIMD (<= 128 VGPRs) for the FP32 modes; the
@@ -593,7 +609,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
     constexpr int NW = BLOCK / 64;
     constexpr bool KAHAN = KH && (PREC == kC32);
     constexpr int NT = (MODE == kLin) ? kTerms : (MODE == kBwd ? 6 : 1);
-    constexpr bool CMP = (MODE == kLin && (PREC == kC32 || PREC == kF64));   // compacted hits
+    // compacted hits: linearize in the compensated and FP64 modes, evaluate in
+    // the compensated mode (the FP64 evaluate measured faster per lane)
+    constexpr bool CMP = (MODE == kLin && (PREC == kC32 || PREC == kF64)) || (MODE == kEval && PREC == kC32);
     // chunks that cannot reach any level's key box are skipped (not in the
     // backward pass, which writes a gradient row for every point, nor in the
     // naive FP32 mode, whose absolute-coordinate keys can be off by more than
@@ -602,7 +620,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
     // a one-level kernel keeps the chunks' anchor keys biased by 8192 in LDS
     // (its only level is the coarse one, so they are the lookup's keys as they are)
     constexpr int32_t KBB = (LM == 1) ? kKeyBias : 0;
-    // one-level compacted linearization: positions in voxel units (the rotation
+    // one-level compacted linearization and evaluation: positions in voxel units (the rotation
     // and the anchor remainders scaled by 1/r), so keys need no multiply
     constexpr bool SC = CMP && PREC == kC32 && LM == 1;
     // the compacted probes issue a chunk's table loads and drain a full wave of
@@ -725,7 +743,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
             if constexpr (CMP) {
                 if (q_count >= kChunk) {
                     __builtin_amdgcn_wave_barrier();
-                    drain_hit<PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, q_head + lane);
+                    drain_hit<MODE, PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, q_head + lane);
                     q_head = (q_head + kChunk) & (kQueue - 1);
                     q_count -= kChunk;
                     __builtin_amdgcn_wave_barrier();
@@ -1174,7 +1192,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 if (q_count > 0) {
                     __builtin_amdgcn_wave_barrier();
                     if (lane < q_count) {
-                        drain_hit<PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, s_q[wave], (q_head + lane) & (kQueue - 1));
+                        drain_hit<MODE, PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, s_q[wave], (q_head + lane) & (kQueue - 1));
                     }
                     __builtin_amdgcn_wave_barrier();
                     q_head = 0;
@@ -1513,10 +1531,11 @@ vg_status launch_tiles(vg_batch* b, const Workspace& ws, int mode, const double*
     if (grid < 1) grid = 1;
     if (t1 <= t0) return VG_OK;
     // FP32 pose copies for the FP32 kernels; the one-level compensated
-    // linearization forms its rotation from the FP64 poses and reads none
-    const bool one_level_lin = mode == kLin && b->opt.precision == kC32 && !b->opt.lane_kahan &&
+    // linearization and evaluation form their rotation from the FP64 poses and
+    // read none
+    const bool one_level_cmp = (mode == kLin || mode == kEval) && b->opt.precision == kC32 && !b->opt.lane_kahan &&
                                !b->opt.surface_validation && b->L == 1;
-    if (b->opt.precision != kF64 && f1 > f0 && !one_level_lin) {
+    if (b->opt.precision != kF64 && f1 > f0 && !one_level_cmp) {
         const int64_t nf = (f1 - f0) * 16;
         k_stage_poses<<<(int)((nf + 255) / 256), 256, 0, b->ctx->stream>>>(f1 - f0, d_poses + 12 * f0,
                                                                           ws.posef + 16 * f0);

@@ -1188,8 +1188,15 @@ extern "C" vg_status vg_backward_async(vg_batch* b, const double* d_poses, const
             b->gslab_bytes = need;
         }
     }
-    if (d_grad_points)
+    if (d_grad_points) {
         VG_TRY(launch_zero(b->ctx, d_grad_points, (size_t)b->grad_rows * 3 * (points_dtype ? 8 : 4)));
+        // the one-level compensated backward kernel writes only the rows of
+        // points with a voxel, so the per-factor rows start at zero too
+        const bool compacted = b->opt.precision == kC32 && !b->opt.lane_kahan && !b->opt.surface_validation &&
+                               b->L == 1;
+        if (compacted && b->slab_rows > 0)
+            VG_TRY(launch_zero(b->ctx, b->d_gslab, (size_t)b->slab_rows * 3 * (points_dtype ? 8 : 4)));
+    }
     const int32_t nt = (int32_t)b->h_tiles.size();
     const Workspace ws = batch_ws(b);
     VG_TRY(launch_tiles(b, ws, kBwd, d_poses, 0, nt, b->grid, d_grad_e, d_grad_points, points_dtype, 0, b->F));

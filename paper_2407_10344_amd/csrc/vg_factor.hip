@@ -318,6 +318,39 @@ __device__ __forceinline__ void point_S(const FactorDesc* __restrict__ Fp, int64
     }
 }
 
+// Gradient of point i (internal order) of a factor: a source used by this
+// factor only is written in place (caller order); a source shared with other
+// factors gets this factor's own rows in the per-factor buffer, summed per
+// source in factor order by k_grad_combine, so the result does not depend on
+// which workgroup finished first.
+__device__ __forceinline__ void write_point_grad(const FactorDesc* __restrict__ Fp, int64_t i, void* grad_points,
+                                                 void* grad_slab, int32_t dtype, double g0, double g1, double g2) {
+    const bool own = Fp->grad_slab < 0;
+    const int64_t row = (own ? Fp->grad_offset : Fp->grad_slab) + Fp->perm[i];
+    void* base = own ? grad_points : grad_slab;
+    if (dtype == 0) {
+        float* g = (float*)base + 3 * row;
+        g[0] = (float)g0;
+        g[1] = (float)g1;
+        g[2] = (float)g2;
+    } else {
+        double* g = (double*)base + 3 * row;
+        g[0] = g0;
+        g[1] = g1;
+        g[2] = g2;
+    }
+}
+
+// Where the backward pass writes point gradients: the upstream gradient of the
+// factor's e, the caller's rows, the per-factor rows of shared sources and the
+// element type (0 FP32, 1 FP64).  Unused when linearizing or evaluating.
+struct GradOut {
+    double ge;
+    void* points;
+    void* slab;
+    int32_t dtype;
+};
+
 // Terms of one queued hit (compensated mode): the same arithmetic as the
 // uncompacted path, with the point's chunk and level taken from the entry.
 // SC (one-level kernels): R is the rotation scaled by 1/r, the chunk data hold
@@ -329,7 +362,8 @@ __device__ __forceinline__ void point_S(const FactorDesc* __restrict__ Fp, int64
 template <int MODE, bool SC, typename A>
 __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restrict__ Fp, const TileShared& sh,
                                               const ProbeLevel& pl0, const double* P, const float* R, int64_t n_pad,
-                                              float dx, float dy, float dz, int32_t i, int32_t v, int32_t cl) {
+                                              float dx, float dy, float dz, int32_t i, int32_t v, int32_t cl,
+                                              const GradOut& go) {
     if constexpr (SC) {
         static_assert(sizeof(ChunkLds) == 48, "the FP64 remainders of a chunk sit at half its byte offset");
         const ChunkLds& cd = *reinterpret_cast<const ChunkLds*>(reinterpret_cast<const char*>(sh.cd) + cl);
@@ -368,8 +402,15 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
             z[a] = fmaf(yl - f32[a], pl0.r, za[a]);
         }
         const double Ct[6] = {cva.x, cva.y, cvb.x, cvb.y, cvc.x, cvc.y};
-        double M[6];
-        rotate_cov_add(R64, C64, Ct, M);
+        double M[6], S[6];
+        if constexpr (MODE == kBwd) {
+            // the backward terms need R C R^T itself
+            rotate_cov(R64, C64, S);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) M[k] = Ct[k] + S[k];
+        } else {
+            rotate_cov_add(R64, C64, Ct, M);
+        }
         float W[6];
         sym3_inverse_f32(M, W);
         // d = mu~ - y in FP64: (voxel mean - centre) - ((anchor remainder - r/2) - jk r + R offset)
@@ -380,7 +421,30 @@ __device__ __forceinline__ void cmp_hit_terms(A& acc, const FactorDesc* __restri
             const double base = fma(-(double)jk[a], pl0.r64, fhv[a]) - (double)mv[a];
             d[a] = -(float)fma(P[3 * a + 2], ddz, fma(P[3 * a + 1], ddy, fma(P[3 * a], ddx, base)));
         }
-        add_hit<MODE>(acc, d, W, z);
+        if constexpr (MODE == kBwd) {
+            // de/dxi terms (target orientation) and the point's row -2 R^T u (source
+            // frame; R from the FP64 pose, as the terms' rotation here is scaled by 1/r)
+            float u[3], Sf[6], Su[3];
+            sym3_mul(W, d, u);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Sf[k] = (float)S[k];
+            sym3_mul(Sf, u, Su);
+            const float q0 = z[0] + Su[0], q1 = z[1] + Su[1], q2 = z[2] + Su[2];
+            acc.add(0, 2.0f * (u[1] * q2 - u[2] * q1));
+            acc.add(1, 2.0f * (u[2] * q0 - u[0] * q2));
+            acc.add(2, 2.0f * (u[0] * q1 - u[1] * q0));
+            acc.add(3, -2.0f * u[0]);
+            acc.add(4, -2.0f * u[1]);
+            acc.add(5, -2.0f * u[2]);
+            if (go.points != nullptr) {
+                const double u0 = u[0], u1 = u[1], u2 = u[2];
+                write_point_grad(Fp, i, go.points, go.slab, go.dtype, go.ge * (-2.0 * (P[0] * u0 + P[3] * u1 + P[6] * u2)),
+                                 go.ge * (-2.0 * (P[1] * u0 + P[4] * u1 + P[7] * u2)),
+                                 go.ge * (-2.0 * (P[2] * u0 + P[5] * u1 + P[8] * u2)));
+            }
+        } else {
+            add_hit<MODE>(acc, d, W, z);
+        }
         return;
     }
     const int c = cl >> 2, l = cl & 3;
@@ -462,9 +526,9 @@ __device__ __forceinline__ void cmp_hit_terms64(A& acc, const FactorDesc* __rest
 template <int MODE, int PREC, bool SC, typename A, typename T>
 __device__ __forceinline__ void drain_hit(A& acc, const FactorDesc* __restrict__ Fp, const TileShared& sh,
                                           const ProbeLevel& pl0, const double* P, const T* R, const T* tt,
-                                          int64_t n_pad, const HitQueue& Q, int e) {
+                                          int64_t n_pad, const HitQueue& Q, int e, const GradOut& go) {
     if constexpr (PREC == kC32)
-        cmp_hit_terms<MODE, SC>(acc, Fp, sh, pl0, P, R, n_pad, Q.x[e], Q.y[e], Q.z[e], Q.pt[e], Q.rec[e], Q.cl[e]);
+        cmp_hit_terms<MODE, SC>(acc, Fp, sh, pl0, P, R, n_pad, Q.x[e], Q.y[e], Q.z[e], Q.pt[e], Q.rec[e], Q.cl[e], go);
     else
         cmp_hit_terms64<MODE>(acc, Fp, P, R, tt, n_pad, Q.pt[e], Q.rec[e], Q.cl[e]);
 }
@@ -515,29 +579,6 @@ __device__ __forceinline__ int chunk_state(const FactorDesc* __restrict__ Fp, co
         reach |= (d2 <= rr * rr) && box;
     }
     return !reach ? kChunkCulled : (inside ? kChunkInside : kChunkStraddles);
-}
-
-// Gradient of point i (internal order) of a factor: a source used by this
-// factor only is written in place (caller order); a source shared with other
-// factors gets this factor's own rows in the per-factor buffer, summed per
-// source in factor order by k_grad_combine, so the result does not depend on
-// which workgroup finished first.
-__device__ __forceinline__ void write_point_grad(const FactorDesc* __restrict__ Fp, int64_t i, void* grad_points,
-                                                 void* grad_slab, int32_t dtype, double g0, double g1, double g2) {
-    const bool own = Fp->grad_slab < 0;
-    const int64_t row = (own ? Fp->grad_offset : Fp->grad_slab) + Fp->perm[i];
-    void* base = own ? grad_points : grad_slab;
-    if (dtype == 0) {
-        float* g = (float*)base + 3 * row;
-        g[0] = (float)g0;
-        g[1] = (float)g1;
-        g[2] = (float)g2;
-    } else {
-        double* g = (double*)base + 3 * row;
-        g[0] = g0;
-        g[1] = g1;
-        g[2] = g2;
-    }
 }
 
 // Point-gradient rows of the shared sources: row k of source s is the sum over
@@ -610,18 +651,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
     constexpr bool KAHAN = KH && (PREC == kC32);
     constexpr int NT = (MODE == kLin) ? kTerms : (MODE == kBwd ? 6 : 1);
     // compacted hits: linearize in the compensated and FP64 modes, evaluate in
-    // the compensated mode (the FP64 evaluate measured faster per lane)
-    constexpr bool CMP = (MODE == kLin && (PREC == kC32 || PREC == kF64)) || (MODE == kEval && PREC == kC32);
+    // the compensated mode (the FP64 evaluate measured faster per lane), and the
+    // one-level compensated backward pass (its caller zeroes the point-gradient
+    // rows, so only points with a voxel write theirs)
+    constexpr bool CMP = (MODE == kLin && (PREC == kC32 || PREC == kF64)) || (MODE == kEval && PREC == kC32) ||
+                         (MODE == kBwd && PREC == kC32 && LM == 1 && !VAL && !KH);
     // chunks that cannot reach any level's key box are skipped (not in the
-    // backward pass, which writes a gradient row for every point, nor in the
-    // naive FP32 mode, whose absolute-coordinate keys can be off by more than
-    // the culling margin far from the origin)
-    constexpr bool SKIP = ((PREC == kC32 || PREC == kF64) && MODE != kBwd);
+    // per-lane backward pass, which writes a gradient row for every point, nor
+    // in the naive FP32 mode, whose absolute-coordinate keys can be off by more
+    // than the culling margin far from the origin)
+    constexpr bool SKIP = ((PREC == kC32 || PREC == kF64) && (MODE != kBwd || CMP));
     // a one-level kernel keeps the chunks' anchor keys biased by 8192 in LDS
     // (its only level is the coarse one, so they are the lookup's keys as they are)
     constexpr int32_t KBB = (LM == 1) ? kKeyBias : 0;
-    // one-level compacted linearization and evaluation: positions in voxel units (the rotation
-    // and the anchor remainders scaled by 1/r), so keys need no multiply
+    // one-level compacted kernels: positions in voxel units (the rotation and
+    // the anchor remainders scaled by 1/r), so keys need no multiply
     constexpr bool SC = CMP && PREC == kC32 && LM == 1;
     // the compacted probes issue a chunk's table loads and drain a full wave of
     // earlier hits while they are in flight, then push the chunk's hits; the
@@ -730,6 +774,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
         int32_t walked_pts = 0, walked_chunks = 0;
         double ge = 0.0;
         if constexpr (MODE == kBwd) ge = grad_e[tile.factor];
+        const GradOut go{ge, grad_points, grad_slab, points_dtype};
 
         // this wave's hit queue (wave-uniform); the head is 0 or 64 (full waves are
         // drained, and the queue restarts at 0 once a batch's rest is drained), so a
@@ -743,7 +788,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
             if constexpr (CMP) {
                 if (q_count >= kChunk) {
                     __builtin_amdgcn_wave_barrier();
-                    drain_hit<MODE, PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, q_head + lane);
+                    drain_hit<MODE, PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, Q, q_head + lane, go);
                     q_head = (q_head + kChunk) & (kQueue - 1);
                     q_count -= kChunk;
                     __builtin_amdgcn_wave_barrier();
@@ -1192,7 +1237,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
                 if (q_count > 0) {
                     __builtin_amdgcn_wave_barrier();
                     if (lane < q_count) {
-                        drain_hit<MODE, PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, s_q[wave], (q_head + lane) & (kQueue - 1));
+                        drain_hit<MODE, PREC, SC>(acc, Fp, sh, pl0, P, R, tt, n_pad, s_q[wave], (q_head + lane) & (kQueue - 1), go);
                     }
                     __builtin_amdgcn_wave_barrier();
                     q_head = 0;
@@ -1530,10 +1575,10 @@ vg_status launch_tiles(vg_batch* b, const Workspace& ws, int mode, const double*
                        int64_t f1) {
     if (grid < 1) grid = 1;
     if (t1 <= t0) return VG_OK;
-    // FP32 pose copies for the FP32 kernels; the one-level compensated
-    // linearization and evaluation form their rotation from the FP64 poses and
-    // read none
-    const bool one_level_cmp = (mode == kLin || mode == kEval) && b->opt.precision == kC32 && !b->opt.lane_kahan &&
+    // FP32 pose copies for the FP32 kernels; the one-level compensated kernels
+    // (linearize, evaluate, backward) form their rotation from the FP64 poses
+    // and read none
+    const bool one_level_cmp = mode != kCount && b->opt.precision == kC32 && !b->opt.lane_kahan &&
                                !b->opt.surface_validation && b->L == 1;
     if (b->opt.precision != kF64 && f1 > f0 && !one_level_cmp) {
         const int64_t nf = (f1 - f0) * 16;

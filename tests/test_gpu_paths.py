@@ -135,12 +135,17 @@ def test_work_counts_follow_culling(vg, c1):
 
 # ----------------------------------------------------------------- shared-source backward
 
+@pytest.mark.parametrize("levels", [4, 1])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-def test_shared_source_backward_is_sum_of_oracle_gradients(vg, c2, dtype):
+def test_shared_source_backward_is_sum_of_oracle_gradients(vg, c2, dtype, levels):
     """The odometry batch matches one new frame against 20 keyframes: every
     factor shares the same source, so its point gradient is the sum of the 20
-    factors' gradients (weighted by grad_e), formed in factor order."""
+    factors' gradients (weighted by grad_e), formed in factor order.  With the
+    maps cut to their 0.5 m level the one-level backward kernel runs, which
+    skips culled chunks and writes only the rows of points with a voxel."""
     vgicp, ctx = vg
+    if levels == 1:
+        c2 = dict(c2, resolutions=(0.5,))
     maps, srcs, batch = vgicp.build_workload(ctx, c2)
     poses = np.array(c2["poses"])
     F = len(poses)
@@ -162,7 +167,7 @@ def test_shared_source_backward_is_sum_of_oracle_gradients(vg, c2, dtype):
         assert rel_err(gxi[f], w[f] * g_o) <= REL
         want += w[f] * gm_o
     err = rel_err(gp.astype(np.float64), want)
-    print("shared source", dtype, "point gradient rel err %.3g" % err, flush=True)
+    print("shared source", dtype, levels, "level(s): point gradient rel err %.3g" % err, flush=True)
     assert err <= REL
     batch.close()
 

@@ -148,7 +148,9 @@ template <typename T, typename A>
 __device__ __forceinline__ void add_lin_terms(A& acc, const T d[3], const T w[6], const T z[3]);
 
 // What one queued hit adds: the 28 terms when linearizing, d^T W d when
-// evaluating (z is then unused).
+// evaluating (z is then unused), the latter with the same operations as the
+// first term of the former, so evaluate's e at a pose is linearize's e at that
+// pose bit for bit (a Levenberg-Marquardt step compares the two)
 template <int MODE, typename T, typename A>
 __device__ __forceinline__ void add_hit(A& acc, const T d[3], const T w[6], const T z[3]) {
     if constexpr (MODE == kLin) {
@@ -156,7 +158,8 @@ __device__ __forceinline__ void add_hit(A& acc, const T d[3], const T w[6], cons
     } else {
         T u[3];
         sym3_mul(w, d, u);
-        acc.add(0, d[0] * u[0] + d[1] * u[1] + d[2] * u[2]);
+        acc.add2(0, d[0], u[0], d[1], u[1]);
+        acc.add(0, d[2] * u[2]);
     }
 }
 
@@ -1250,8 +1253,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(waves_per
         }
         // ---------------------------------------------------------------- reduction of the tile
         // lanes -> wave -> tile: FP64 except kN32, which stays FP32 end to end
-        if constexpr (PREC != kN32 && NT == kTerms) {
-            // the 28 terms in one transposed butterfly (value k ends on lanes 2k, 2k + 1)
+        if constexpr (PREC != kN32 && (NT == kTerms || (CMP && MODE == kEval))) {
+            // the 28 terms in one transposed butterfly (value k ends on lanes 2k, 2k + 1);
+            // the compacted evaluate sums its one term the same way, so its e equals
+            // linearize's
             double v[32];
 #pragma unroll
             for (int k = 0; k < 32; ++k) v[k] = k < NT ? acc.get64(k) : 0.0;

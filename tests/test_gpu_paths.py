@@ -7,6 +7,7 @@
   linearize / evaluate / overlap, fewer walked points once chunks are culled;
 * point gradients of a source shared by several factors: the sum of the
   oracle's per-factor gradients, bit-identical from one call to the next;
+* evaluate's e equal to linearize's e bit for bit in the compensated mode;
 * the compensated mode's extent limit (a source spanning kilometres is refused);
 * FP32-compensated central differences at h = 1e-4 within their rounding bound.
 """
@@ -169,6 +170,25 @@ def test_shared_source_backward_is_sum_of_oracle_gradients(vg, c2, dtype, levels
     err = rel_err(gp.astype(np.float64), want)
     print("shared source", dtype, levels, "level(s): point gradient rel err %.3g" % err, flush=True)
     assert err <= REL
+    batch.close()
+
+
+# ----------------------------------------------------------------- evaluate and linearize agree
+
+@pytest.mark.parametrize("levels", [4, 1])
+def test_evaluate_e_equals_linearize_e(vg, c2, levels):
+    """In the compensated mode evaluate and linearize queue the same hits, process
+    them in the same lanes with the same operations for e and sum e the same
+    way, so evaluate's e at a pose is linearize's e at that pose bit for bit (a
+    Levenberg-Marquardt step accepts a candidate by comparing the two)."""
+    vgicp, ctx = vg
+    cfg = c2 if levels == 4 else dict(c2, resolutions=(0.5,))
+    maps, srcs, batch = vgicp.build_workload(ctx, cfg)
+    for poses in (np.array(cfg["poses"]), np.array(cfg["poses_true"])):
+        e, H, b, inl = batch.linearize(poses)
+        e_eval = np.asarray(batch.evaluate(poses))
+        print(levels, "level(s): max |e_eval - e_lin| / e = %.3g" % float(np.max(np.abs(e_eval - e) / e)), flush=True)
+        assert np.array_equal(e_eval, e)
     batch.close()
 
 

@@ -232,7 +232,10 @@ vg_status vg_linearize(vg_batch* batch, const double* poses, double* e, double* 
                        int64_t* inliers);
 /* Error only, e = sum d^T W d over points and levels (Eq. (em), Eq. (d2d)), with
  * correspondences and W recomputed at the given poses (host arrays: poses
- * F x 12 in, e F out; synchronous). */
+ * F x 12 in, e F out; synchronous).  In the compensated FP32 mode e equals the
+ * e vg_linearize returns at the same poses bit for bit (same hits, same
+ * operations, same order of summation), so comparing the two, as an LM step
+ * does, reflects the pose change only. */
 vg_status vg_evaluate(vg_batch* batch, const double* poses, double* e);
 
 /* Overlap rate of every factor at its pose (GLIM Sec. IV-B and V: the
